@@ -1,0 +1,269 @@
+"""Independent checks of a Polylla result.
+
+These are written from the paper's definitions (Section 3.1: longest-edge
+propagation path, terminal-edge region, frontier edge, barrier tip) and from
+plain geometry and topology, not from the oracle's phases:
+
+  * Lepp walks from every triangle, grouped by terminal edge (Definitions 1-2);
+  * connected components of triangles (scipy's csgraph) across non-frontier
+    edges;
+  * twins from a Python dict of directed edges;
+  * middle edges found by sorting a tip's neighbours by angle (atan2);
+  * loop areas by the shoelace formula, the Euler characteristic of the
+    frontier graph, and the loop structure of next/prev.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# --------------------------------------------------------------------------
+# fixtures
+# --------------------------------------------------------------------------
+
+def load_fixture(name: str) -> dict:
+    verts, tris, expect, polys = [], [], {}, []
+    mode = None
+    with open(os.path.join(GOLDEN, name)) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            if line in ("vertices", "triangles"):
+                mode = line
+                continue
+            parts = line.split()
+            if parts[0] == "expect":
+                key, vals = parts[1], [int(v) for v in parts[2:]]
+                if key == "polygon":
+                    polys.append(sorted(vals))
+                elif len(vals) == 1 and key not in ("seeds", "loop_he", "next", "prev", "loop_off"):
+                    expect[key] = vals[0]
+                else:
+                    expect[key] = vals
+                continue
+            vals = [int(v) for v in parts]
+            (verts if mode == "vertices" else tris).append(vals)
+    return {"xy": np.array(verts, np.int32), "tri": np.array(tris, np.int32),
+            "expect": expect, "polygons": sorted(polys)}
+
+
+def paper_grid(n: int):
+    """The grid generator of Section 7.1 (Algorithm 15) for n points: a
+    floor(sqrt(n)) square of unit-spaced points, vertex k at (k // s, k % s),
+    and two triangles per cell, (k, k+1, k+s+1) and (k, k+s+1, k+s), which
+    come out clockwise."""
+    s = int(math.isqrt(n))
+    xy = np.array([(k // s, k % s) for k in range(s * s)], np.int32)
+    tri = []
+    for k in range(n - s):
+        if k % s != s - 1 and k + s + 1 < s * s:
+            tri.append((k, k + 1, k + s + 1))
+            tri.append((k, k + s + 1, k + s))
+    return xy, np.array(tri, np.int32)
+
+
+# --------------------------------------------------------------------------
+# half-edge helpers (implicit triangle layout h = 3t + i)
+# --------------------------------------------------------------------------
+
+def nxt(h):
+    return np.where(h % 3 == 2, h - 2, h + 1)
+
+
+def twins_by_dict(org: np.ndarray) -> np.ndarray:
+    """Twin of each half-edge from a dict keyed by directed edge."""
+    nh = len(org)
+    tgt = org[nxt(np.arange(nh))]
+    where = {}
+    for h in range(nh):
+        key = (int(org[h]), int(tgt[h]))
+        assert key not in where, "repeated directed edge"
+        where[key] = h
+    tw = np.full(nh, -1, np.int64)
+    for h in range(nh):
+        tw[h] = where.get((int(tgt[h]), int(org[h])), -1)
+    return tw
+
+
+def sq_lengths(xy, org):
+    h = np.arange(len(org))
+    a = xy[org].astype(np.int64)
+    b = xy[org[nxt(h)]].astype(np.int64)
+    d = b - a
+    return d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+
+
+def longest_local(xy, org, twin):
+    """Local index (0..2) of each triangle's longest edge: larger squared
+    length first, then lower edge id min(h, twin(h))."""
+    nt = len(org) // 3
+    l2 = sq_lengths(xy, org).reshape(nt, 3)
+    h = np.arange(3 * nt)
+    eid = np.where((twin >= 0) & (twin < h), twin, h).reshape(nt, 3)
+    best = np.zeros(nt, np.int64)
+    for i in (1, 2):
+        cur_l = l2[np.arange(nt), best]
+        cur_id = eid[np.arange(nt), best]
+        better = (l2[:, i] > cur_l) | ((l2[:, i] == cur_l) & (eid[:, i] < cur_id))
+        best = np.where(better, i, best)
+    return best
+
+
+def tri_components(nt: int, twin: np.ndarray, cut: np.ndarray) -> np.ndarray:
+    """Component label per triangle, joining triangles across every interior
+    edge whose half-edge is not marked in `cut`."""
+    h = np.nonzero((twin >= 0) & ~cut)[0]
+    a, b = h // 3, twin[h] // 3
+    g = coo_matrix((np.ones(len(h), np.int8), (a, b)), shape=(nt, nt))
+    _, lab = connected_components(g, directed=False)
+    return lab
+
+
+# --------------------------------------------------------------------------
+# Definitions 1-3 by brute force
+# --------------------------------------------------------------------------
+
+def lepp_terminal(xy, org, twin):
+    """For every triangle, the terminal edge (as its lower half-edge) at the
+    end of its longest-edge propagation path (Definition 1)."""
+    nt = len(org) // 3
+    L = longest_local(xy, org, twin)
+    term = np.empty(nt, np.int64)
+    for t in range(nt):
+        cur, steps = t, 0
+        while True:
+            e = 3 * cur + int(L[cur])
+            g = int(twin[e])
+            if g < 0:
+                term[t] = e
+                break
+            nb = g // 3
+            if 3 * nb + int(L[nb]) == g:
+                term[t] = min(e, g)
+                break
+            cur = nb
+            steps += 1
+            assert steps <= nt, "Lepp did not end"
+    return term
+
+
+def same_partition(a: np.ndarray, b: np.ndarray) -> bool:
+    """True when the two labelings group the items identically."""
+    pairs = np.unique(np.stack([a, b], 1), axis=0)
+    return len(pairs) == len(np.unique(a)) == len(np.unique(b))
+
+
+def tips_and_middles_geometric(xy, org, twin, frontier):
+    """Barrier tips (vertices on exactly one frontier edge) and, for each, the
+    middle edge reached by floor(degree/2) clockwise steps from its frontier
+    edge, where clockwise order comes from sorting neighbours by angle."""
+    nh = len(org)
+    tgt = org[nxt(np.arange(nh))]
+    fcount = {}
+    for h in range(nh):
+        if frontier[h] and (twin[h] < 0 or h < twin[h]):
+            for v in (int(org[h]), int(tgt[h])):
+                fcount[v] = fcount.get(v, 0) + 1
+    nbrs = {}
+    for h in range(nh):
+        nbrs.setdefault(int(org[h]), set()).add(int(tgt[h]))
+        nbrs.setdefault(int(tgt[h]), set()).add(int(org[h]))
+    fnb = {}
+    for h in range(nh):
+        if frontier[h]:
+            fnb.setdefault(int(org[h]), set()).add(int(tgt[h]))
+    out = []
+    for v, c in sorted(fcount.items()):
+        if c != 1:
+            continue
+        (u,) = fnb[v]
+        ring = sorted(nbrs[v], key=lambda w: -math.atan2(int(xy[w][1]) - int(xy[v][1]),
+                                                           int(xy[w][0]) - int(xy[v][0])))
+        k = ring.index(u)
+        w = ring[(k + len(ring) // 2) % len(ring)]  # descending angle = clockwise
+        out.append((v, w))
+    return out
+
+
+# --------------------------------------------------------------------------
+# invariants of an output (next', prev', seeds, loops)
+# --------------------------------------------------------------------------
+
+def check_output(xy, org, twin, next_o, prev_o, seeds, loop_off, loop_he, disk=True):
+    """Asserts the structural invariants of a Polylla output and returns the
+    per-triangle polygon labels and a few counts."""
+    xy = np.asarray(xy, np.int64)
+    nh = len(org)
+    nt = nh // 3
+    h = np.arange(nh)
+    tgt = org[nxt(h)]
+    next_o = np.asarray(next_o, np.int64)
+    prev_o = np.asarray(prev_o, np.int64)
+    seeds = np.asarray(seeds, np.int64)
+    loop_off = np.asarray(loop_off, np.int64)
+    loop_he = np.asarray(loop_he, np.int64)
+    P = len(seeds)
+    assert len(loop_off) == P + 1 and loop_off[0] == 0 and loop_off[-1] == len(loop_he)
+    assert np.all(np.diff(loop_off) >= 1)
+    # each half-edge is on at most one loop; F' = the linked half-edges
+    assert len(np.unique(loop_he)) == len(loop_he)
+    onloop = np.zeros(nh, bool)
+    onloop[loop_he] = True
+    assert np.array_equal(next_o >= 0, onloop)
+    assert np.array_equal(prev_o >= 0, onloop)
+    # F' is a set of edges: both halves of an interior edge, or neither
+    inter = twin >= 0
+    assert np.array_equal(onloop[inter], onloop[twin[inter]])
+    # boundary edges are always frontier
+    assert np.all(onloop[~inter])
+    # linking: next' continues at the target, prev' inverts next'
+    f = np.nonzero(onloop)[0]
+    assert np.array_equal(org[next_o[f]], tgt[f])
+    assert np.array_equal(prev_o[next_o[f]], f)
+    # no barrier tip left: no loop turns back along the same edge
+    assert not np.any(next_o[f] == twin[f])
+    # loops follow next', start at their minimum, minima ascending
+    starts = loop_off[:-1]
+    assert np.array_equal(loop_he[starts], seeds)
+    if P > 1:
+        assert np.all(np.diff(seeds) > 0)
+    pos_next = np.roll(np.arange(len(loop_he)), -1)
+    pos_next[loop_off[1:] - 1] = starts
+    assert np.array_equal(next_o[loop_he], loop_he[pos_next])
+    loop_id = np.repeat(np.arange(P), np.diff(loop_off))
+    assert np.array_equal(np.minimum.reduceat(loop_he, starts), seeds)
+    # polygons: triangles joined across non-F' edges; one loop per polygon
+    comp = tri_components(nt, twin, onloop)
+    loop_comp = comp[loop_he // 3]
+    first = loop_comp[starts]
+    assert np.array_equal(loop_comp, first[loop_id]), "a loop spans two polygons"
+    assert len(np.unique(first)) == P == len(np.unique(comp)), "polygons and loops differ"
+    # each loop is exactly the F' half-edges of its polygon's triangles
+    owner = np.full(len(np.unique(comp)), -1, np.int64)
+    owner[first] = np.arange(P)
+    loop_of = np.full(nh, -1, np.int64)
+    loop_of[loop_he] = loop_id
+    assert np.array_equal(loop_of[f], owner[comp[f // 3]])
+    # areas (twice the signed area, exact in int64 for coordinates <= 2^30 per term)
+    cross = xy[org, 0] * xy[tgt, 1] - xy[tgt, 0] * xy[org, 1]
+    tri_area = cross.reshape(nt, 3).sum(1)
+    assert np.all(tri_area > 0)
+    loop_area = np.add.reduceat(cross[loop_he], starts) if P else np.zeros(0, np.int64)
+    comp_area = np.zeros(len(owner), np.int64)
+    np.add.at(comp_area, comp, tri_area)
+    assert np.array_equal(loop_area, comp_area[first])
+    # Euler characteristic of the frontier graph of a disk: V - E + P = 1
+    nedge = int(np.count_nonzero(onloop & ~inter) + np.count_nonzero(onloop & inter) // 2)
+    nvert = len(np.unique(org))
+    if disk:
+        assert nvert - nedge + P == 1
+    return {"comp": comp, "P": P, "Fh": len(loop_he), "E": nedge, "V": nvert,
+            "total_area2": int(tri_area.sum()), "onloop": onloop}
