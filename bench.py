@@ -1,0 +1,218 @@
+"""Benchmark: Mtri/s of on-device Polylla meshing (label -> relink -> repair ->
+walk -> compact) on one MI355X, half-edge structure resident in HBM.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--no-cpu] [--kernel-profile]
+
+Prints one JSON line.  A step is one run of the whole meshing chain over the
+workload (default: the 4096 x 4096-cell warped grid, 33,554,432 triangles).
+The build of the half-edge structure (orientation + twin matching) and the
+host<->device copies are timed separately and reported beside the headline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "plain_4096x4096_warped": "plain_large_warped",
+    "plain_1024x1024": "plain_scale",
+    "plain_32x32": "plain_small",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(nt, nv, npoly, nloop):
+    """Bytes the meshing chain must move per run: read org, twin (3T int32
+    each) and xy (2V int32); write next, prev (3T int32 each), seeds (P),
+    loop_off (P+1) and loop_he (Fh) -- 48T + 8V + 8P + 4Fh (+4)."""
+    return 48 * nt + 8 * nv + 8 * npoly + 4 * nloop + 4
+
+
+def kernel_bytes(name, nt, nv, npoly, nloop):
+    """Algorithmic bytes of one launch of each kernel."""
+    return {
+        "k_label": 12 * nt + 8 * nv + 2 * nt,                 # org, xy -> tflag, pl
+        "k_relink": 12 * nt + nt + 24 * nt,                   # twin, tflag -> next, prev
+        "k_walk": nt + 4 * nloop + npoly,                     # tflag, next along loops -> pl
+        "k_compact": nt + 4 * nloop + 8 * npoly + 4 * nloop,  # pl, next -> seeds, loop_off, loop_he
+    }.get(name)
+
+
+def cpu_baseline(mesh):
+    """The oracle, single-threaded, on the whole workload (one run)."""
+    import oracle
+    t0 = time.perf_counter()
+    res = oracle.polylla(mesh.xy, mesh.tri)
+    wall = time.perf_counter() - t0
+    st = res.stats
+    mesh_ms = st["ms_label"] + st["ms_repair"] + st["ms_traverse"] + st["ms_canon"]
+    return {
+        "value": round(mesh.nt / (mesh_ms * 1e-3) / 1e6, 3),
+        "unit": "Mtri/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one oracle run over the whole {mesh.name} mesh ({mesh.nt} triangles); value = "
+                  f"meshing phases only (label+repair+traversal+canonical order, {mesh_ms:.0f} ms); "
+                  f"the half-edge build took {st['ms_build']:.0f} ms more; wall {wall:.1f} s",
+        "build_plus_mesh_mtri_s": round(mesh.nt / ((mesh_ms + st["ms_build"]) * 1e-3) / 1e6, 3),
+    }, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain_4096x4096_warped", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--check", action="store_true", help="compare the GPU result with the oracle")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the pipeline runs on a single device); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2403_14723_amd as gp
+    from paper_2403_14723_amd import workloads as W
+
+    t0 = time.perf_counter()
+    mesh = getattr(W, WORKLOADS[args.workload])()
+    log(f"[bench] generated {mesh.name}: V={mesh.nv} T={mesh.nt} in {time.perf_counter() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    # a dedicated stream (handle != 0) shared by torch and the library, so
+    # torch's copies and events are ordered with the library's kernels
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+    ctx = gp.Context(0, stream=stream.cuda_stream, profile=True)
+
+    # host -> device copy of the inputs from pinned memory (reported apart)
+    xy_h = torch.from_numpy(mesh.xy).pin_memory()
+    tri_h = torch.from_numpy(mesh.tri).pin_memory()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    xy_d = xy_h.to(dev, non_blocking=True)
+    tri_d = tri_h.to(dev, non_blocking=True)
+    e1.record(stream)
+    h = ctx.build_halfedges(xy_d, tri_d)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = e0.elapsed_time(e1)
+    build_ms = e1.elapsed_time(e2)
+    log(f"[bench] H2D {h2d_ms:.2f} ms, build {build_ms:.2f} ms")
+
+    for _ in range(args.warmup):
+        r = ctx.mesh(h, gp.GP_ASYNC)
+        r.free()
+    ctx.sync()
+    ctx.kernel_reset()
+    log(f"[bench] warmup done; timing {args.steps} steps")
+
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        r = ctx.mesh(h, gp.GP_ASYNC)
+        r.free()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - w0
+    ctx.sync()
+    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    kms = ctx.kernel_ms()
+    log(f"[bench] {ms_per_step:.3f} ms/step (wall {wall_s * 1e3 / args.steps:.3f} ms/step)")
+
+    # one more run for counts and the device->host copy time of all outputs
+    # into pinned host buffers (reported apart from the headline)
+    r = ctx.mesh(h)
+    info = r.info()
+    nh, P, Fh = info["nh"], info["npoly"], info["nloop_he"]
+    bufs = [torch.empty(max(n, 1), dtype=torch.int32).pin_memory() for n in (nh, nh, P, P + 1, Fh)]
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    d0.record(stream)
+    rc = gp.library().gpolylla_result_copy(r.handle, *[b.data_ptr() for b in bufs])
+    d1.record(stream)
+    torch.cuda.synchronize()
+    assert rc == gp.GP_OK, rc
+    d2h_ms = d0.elapsed_time(d1)
+    check = None
+    if args.check:
+        import oracle
+        o = oracle.polylla(mesh.xy, mesh.tri)
+        g = r.copy()
+        check = all(np.array_equal(g[k], getattr(o, k)) for k in ("next", "prev", "seeds", "loop_off", "loop_he"))
+    r.free()
+
+    nt, nv = mesh.nt, mesh.nv
+    P, Fh = info["npoly"], info["nloop_he"]
+    b_alg = algorithmic_bytes(nt, nv, P, Fh)
+    kernels = {}
+    for name, (avg, cnt) in kms.items():
+        kb = kernel_bytes(name, nt, nv, P, Fh)
+        kernels[name] = {"avg_ms": round(avg, 5), "launches": cnt}
+        if kb and avg > 0:
+            kernels[name]["alg_GBs"] = round(kb / (avg * 1e-3) / 1e9, 1)
+    dom = max((k for k in kms if kernel_bytes(k, nt, nv, P, Fh)), key=lambda k: kms[k][0])
+    dom_ms = kms[dom][0]
+    dom_bytes = kernel_bytes(dom, nt, nv, P, Fh)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    value = nt / (ms_per_step * 1e-3) / 1e6
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline (single thread)")
+        cpu, _ = cpu_baseline(mesh)
+
+    line = {
+        "metric": "Mtri/s meshed on-device (label->relink->walk->repair); batched vs plain; p99 lat",
+        "value": round(value, 2),
+        "unit": "Mtri/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": mesh.name, "triangles": nt, "vertices": nv,
+                   "polygons": P, "loop_half_edges": Fh, "tips": info["ntips"],
+                   "ties": info["nties"], "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": dom_bytes},
+        "whole_path": {"alg_bytes": b_alg, "alg_GBs": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
+                       "frac": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels": kernels,
+        "separate": {"h2d_ms": round(h2d_ms, 3), "build_ms": round(build_ms, 3), "d2h_ms": round(d2h_ms, 3),
+                     "with_copies_mtri_s": round(nt / ((h2d_ms + build_ms + ms_per_step + d2h_ms) * 1e-3) / 1e6, 2)},
+        "cpu_baseline": cpu,
+    }
+    if check is not None:
+        line["oracle_match"] = check
+    print(json.dumps(line), flush=True)
+    h.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

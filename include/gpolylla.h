@@ -1,0 +1,175 @@
+/*
+ * gpolylla: Polylla polygonal meshing of 2-D triangulations on MI355X (gfx950).
+ *
+ * The problem statement follows the paper (Section 1 and Section 4.2): a
+ * triangulation tau = (V, E) goes in as vertex coordinates and triangle index
+ * triples; it is held as a half-edge structure on the device; the output is
+ * the same half-edge structure with next/prev of the frontier half-edges
+ * relinked so that each polygon of the Polylla mesh is one next-cycle, plus
+ * one seed half-edge per polygon (Section 4.3: "output seed edges").
+ *
+ * Conventions (fixed where the paper leaves a choice open):
+ *   - coordinates are int32 in [0, 2^30]; edge lengths are compared as exact
+ *     int64 squared lengths; on equal squared length the edge with the lower
+ *     id min(h, twin(h)) counts as longer;
+ *   - each triangle is stored counter-clockwise (a clockwise triple (a,b,c)
+ *     is stored as (a,c,b)); half-edge h = 3t+i starts at corner i of
+ *     triangle t, next(h) = 3t+(i+1)%3, prev(h) = 3t+(i+2)%3; boundary
+ *     half-edges have twin -1 (there are no exterior half-edges);
+ *   - barrier tips (Section 3.1) are repaired in one pass from the
+ *     label-phase frontier: for a tip v whose single frontier edge leaves v as
+ *     a, the edge reached by floor(degree(v)/2) clockwise turns from a
+ *     (CW(h) = next(twin(h))) becomes a frontier edge;
+ *   - outputs: next[h], prev[h] = -1 for half-edges not on any polygon;
+ *     seeds[p] ascending, each the minimum half-edge of its polygon's loop;
+ *     loop_he[loop_off[p] .. loop_off[p+1]) is loop p starting at seeds[p]
+ *     and following next.  All indices are local to their mesh.
+ *
+ * Return values: 0 (GP_OK) or a negative GP_E* code; gpolylla_strerror()
+ * names it.  Functions never abort the process.
+ *
+ * Threading: a gp_ctx and everything built from it belong to one host thread
+ * at a time.  A gp_server is safe to use from many threads.
+ *
+ * Lifetime: meshes and results hold memory of their context's pool; free them
+ * before destroying the context.  Device memory released by a free is reused
+ * only by later work on the same context stream, so frees never wait for the
+ * GPU.
+ */
+#ifndef GPOLYLLA_H
+#define GPOLYLLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define GP_OK 0
+#define GP_EINVAL (-1)        /* null pointer, negative count, vertex index outside [0, nv) */
+#define GP_ERANGE (-2)        /* coordinate outside [0, 2^30], or 3*nt >= 2^31 */
+#define GP_EDEGEN (-3)        /* zero-area triangle */
+#define GP_ENONMANIFOLD (-4)  /* an edge in more than two triangles, or a repeated directed edge */
+#define GP_ENOMEM (-5)        /* device or pinned-host allocation failed, or the pool cap was hit */
+#define GP_EHIP (-6)          /* a HIP runtime call failed */
+#define GP_EAGAIN (-7)        /* server queue full */
+#define GP_ETOOBIG (-8)       /* request footprint exceeds the server pool */
+#define GP_ETIMEDOUT (-9)     /* wait timed out */
+#define GP_ECORRUPT (-10)     /* a rotation, walk or scan guard tripped: the half-edge
+                                 structure is not a valid manifold triangulation */
+
+/* ---- flags -------------------------------------------------------------- */
+#define GP_IN_DEVICE 0x1u     /* build: xy and tri are device pointers on the context's device */
+#define GP_ASYNC 0x2u         /* mesh: return once the work is queued; counts are read
+                                 (and errors reported) by the first result query */
+#define GP_OUT_LOOPS 0x10u    /* mesh: also produce seeds / loop_off / loop_he (default on) */
+#define GP_OUT_NO_LOOPS 0x20u /* mesh: only next/prev and the counts */
+
+typedef struct gp_ctx gp_ctx;
+typedef struct gp_mesh gp_mesh;
+typedef struct gp_result gp_result;
+typedef struct gp_server gp_server;
+
+typedef struct {
+    size_t pool_bytes;  /* cap on device memory held by the context's pool; 0 = no cap */
+    void *stream;       /* hipStream_t to run on; NULL = the context creates its own */
+    int32_t profile;    /* 1 = record per-kernel HIP events (see gpolylla_ctx_kernel_ms) */
+    int32_t block;      /* threads per block for the streaming kernels; 0 = tuned default */
+    int32_t items;      /* items per thread for the streaming kernels; 0 = tuned default */
+} gp_ctx_opts;
+
+typedef struct {
+    int64_t nt, nv, nh;   /* triangles, vertices, half-edges (3*nt) */
+    int64_t npoly;        /* polygons (= seeds) */
+    int64_t nloop_he;     /* half-edges on loops */
+    int64_t nterminal;    /* terminal edges (interior and boundary) */
+    int64_t ntips;        /* barrier tips repaired */
+    int64_t nmiddle;      /* distinct middle edges added by the repair */
+    int64_t nties;        /* triangles whose largest squared length is shared */
+    int64_t nflipped;     /* triangles given clockwise (from the build) */
+} gp_result_info;
+
+typedef struct {      /* device views of a result (valid until gpolylla_result_free) */
+    int32_t *next, *prev, *seeds, *loop_off, *loop_he;
+} gp_result_dev;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`.  opts may be NULL. */
+int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out);
+void gpolylla_ctx_destroy(gp_ctx *ctx);
+/* Bytes currently held by the context's device pool (in use + cached). */
+int gpolylla_ctx_pool_bytes(const gp_ctx *ctx, size_t *held, size_t *in_use);
+/* With profile = 1: average device milliseconds per launch of each pipeline
+ * kernel over the launches since the last reset.  names[i] receives a static
+ * string.  Returns the number of kernels written (<= cap). */
+int gpolylla_ctx_kernel_ms(gp_ctx *ctx, const char **names, double *avg_ms, int64_t *launches, int cap);
+void gpolylla_ctx_kernel_reset(gp_ctx *ctx);
+
+/* ---- build -------------------------------------------------------------- */
+
+/*
+ * Builds the half-edge structure of a triangulation on the device
+ * (Section 4.1-4.2): validation, counter-clockwise orientation (exact int64
+ * orientation test) and twin matching (bucket half-edges by origin, then look
+ * for the reverse edge in the target's bucket).
+ *   xy:  2*nv int32, interleaved (x0, y0, x1, y1, ...)
+ *   tri: 3*nt int32 vertex indices
+ * Host pointers unless flags has GP_IN_DEVICE.  The inputs are copied; the
+ * caller keeps ownership and may free them when the call returns.  On
+ * success *out is a device-resident mesh owned by the caller (free it with
+ * gpolylla_mesh_free).  Errors: GP_EINVAL, GP_ERANGE, GP_EDEGEN,
+ * GP_ENONMANIFOLD, GP_ENOMEM, GP_EHIP.  Synchronous.
+ */
+int gpolylla_build_halfedges(gp_ctx *ctx, const int32_t *xy, int32_t nv, const int32_t *tri,
+                             int32_t nt, uint32_t flags, gp_mesh **out);
+/* Copies the oriented corner list (org, 3*nt) and twins (3*nt) to host buffers;
+ * either may be NULL.  nflipped (may be NULL) receives the re-oriented count. */
+int gpolylla_mesh_copy(const gp_mesh *mesh, int32_t *org, int32_t *twin, int64_t *nflipped);
+int gpolylla_mesh_size(const gp_mesh *mesh, int32_t *nv, int32_t *nt);
+void gpolylla_mesh_free(gp_mesh *mesh);
+
+/* ---- meshing ------------------------------------------------------------ */
+
+/*
+ * Runs the Polylla pipeline on one resident mesh: longest-edge, frontier and
+ * seed labelling (Section 6.1-6.3), relinking next/prev of frontier
+ * half-edges (Section 6.5), barrier-tip repair (Section 6.4, one pass), seed
+ * walks to each loop's minimum (Sections 6.5.1-6.6) and compaction of the
+ * seeds and loops (Section 6.7).  The mesh is not modified.  On success *out
+ * holds device-resident results owned by the caller.  Errors: GP_EINVAL,
+ * GP_ENOMEM, GP_EHIP, GP_ECORRUPT.  Synchronous unless GP_ASYNC.
+ */
+int gpolylla_mesh(gp_ctx *ctx, const gp_mesh *mesh, uint32_t out_flags, gp_result **out);
+
+/*
+ * Runs n meshes as one batch: every kernel of the pipeline is launched once
+ * for all meshes over a flattened tile space with a per-mesh descriptor
+ * table, so uneven sizes share launches.  Results are identical to n calls
+ * of gpolylla_mesh; out[i] belongs to meshes[i].  Meshes may repeat.
+ */
+int gpolylla_mesh_batch(gp_ctx *ctx, const gp_mesh *const *meshes, int32_t n, uint32_t out_flags,
+                        gp_result **out);
+
+/* Counts of a result (waits for an asynchronous run). */
+int gpolylla_result_info(gp_result *res, gp_result_info *info);
+/* Copies outputs to caller-allocated host buffers sized from the info
+ * (next, prev: nh; seeds: npoly; loop_off: npoly+1; loop_he: nloop_he).
+ * NULL skips an output. */
+int gpolylla_result_copy(gp_result *res, int32_t *next, int32_t *prev, int32_t *seeds,
+                         int32_t *loop_off, int32_t *loop_he);
+/* Device pointers of the outputs, for zero-copy consumers. */
+int gpolylla_result_device(gp_result *res, gp_result_dev *dev);
+void gpolylla_result_free(gp_result *res);
+
+/* Waits until all queued work of the context has finished. */
+int gpolylla_ctx_sync(gp_ctx *ctx);
+
+const char *gpolylla_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

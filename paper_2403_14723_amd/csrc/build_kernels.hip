@@ -1,0 +1,223 @@
+// Half-edge construction on the device (the structure of Section 4.1-4.2,
+// built on the GPU instead of the host).
+//
+//   k_check_xy   coordinates in [0, 2^30]
+//   k_orient     index check, exact int64 orientation test, counter-clockwise
+//                corner order, out-degree count per vertex
+//   k_scan_excl  exclusive scan of the out-degrees (decoupled look-back)
+//   k_bucket     half-edges grouped by origin vertex (CSR)
+//   k_match      twin(h) for h = u->v: the half-edge v->u in v's bucket; a
+//                second u->v in u's bucket, or two v->u, is non-manifold
+//
+// Errors are reduced with a 64-bit atomicMin over (rank << 8 | code) so the
+// reported code is deterministic: coordinate range first, then the lowest
+// bad triangle, then the lowest non-manifold half-edge.
+#include "gp_internal.h"
+
+namespace gp {
+
+namespace {
+
+constexpr int kCoordMax = 1 << 30;
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr uint64_t kScanAgg = 1ull << 62;
+constexpr uint64_t kScanInc = 2ull << 62;
+
+__device__ __forceinline__ unsigned long long err_key(unsigned long long rank, int code) {
+    return (rank << 8) | (unsigned long long)(-code);
+}
+
+__device__ __forceinline__ int he_next_b(int h) {
+    int t = h / 3;
+    return (h - 3 * t == 2) ? h - 2 : h + 1;
+}
+
+__global__ void k_check_xy(const int2 *__restrict__ xy, int nv, unsigned long long *err) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        int2 p = xy[v];
+        if (p.x < 0 || p.x > kCoordMax || p.y < 0 || p.y > kCoordMax) atomicMin(err, err_key(0, -2));
+    }
+}
+
+__global__ void k_orient(const int2 *__restrict__ xy, const int32_t *__restrict__ tri, int nv, int nt,
+                         int32_t *__restrict__ org, int32_t *__restrict__ deg,
+                         unsigned long long *err, int32_t *nflipped) {
+    for (int base = blockIdx.x * blockDim.x; base < nt; base += gridDim.x * blockDim.x) {
+        int t = base + threadIdx.x;
+        bool flip = false;
+        if (t < nt) {
+            int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+            if ((unsigned)a >= (unsigned)nv || (unsigned)b >= (unsigned)nv || (unsigned)c >= (unsigned)nv) {
+                atomicMin(err, err_key(1ull + t, -1));
+            } else {
+                int2 pa = xy[a], pb = xy[b], pc = xy[c];
+                long long o = ((long long)pb.x - pa.x) * ((long long)pc.y - pa.y) -
+                              ((long long)pb.y - pa.y) * ((long long)pc.x - pa.x);
+                if (o == 0) {
+                    atomicMin(err, err_key(1ull + t, -3));
+                } else {
+                    if (o < 0) {
+                        int s = b;
+                        b = c;
+                        c = s;
+                        flip = true;
+                    }
+                    org[3 * t] = a;
+                    org[3 * t + 1] = b;
+                    org[3 * t + 2] = c;
+                    atomicAdd(&deg[a], 1);
+                    atomicAdd(&deg[b], 1);
+                    atomicAdd(&deg[c], 1);
+                }
+            }
+        }
+        unsigned long long m = __ballot(flip);
+        if (m && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(nflipped, __popcll(m));
+    }
+}
+
+// Exclusive scan of in[0, n) into out[0, n], out[n] = total.  One pass with
+// dynamically numbered tiles and decoupled look-back.
+__global__ void __launch_bounds__(kScanBlock) k_scan_excl(const int32_t *__restrict__ in, int32_t *out,
+                                                           int n, uint64_t *status, int32_t *tile_ctr,
+                                                           unsigned long long *err) {
+    __shared__ int s_tile;
+    __shared__ int s_wave[kScanBlock / 64];
+    __shared__ int s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1);
+    __syncthreads();
+    const int tile = s_tile;
+    const int i0 = tile * kScanBlock * kScanItems + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        v[j] = (i0 + j < n) ? in[i0 + j] : 0;
+        sum += v[j];
+    }
+    // block exclusive scan of the per-thread sums
+    int lane = __lane_id(), w = threadIdx.x / 64;
+    int x = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wave[w] = x;
+    __syncthreads();
+    int wave_off = 0, total = 0;
+    for (int k = 0; k < kScanBlock / 64; k++) {
+        if (k < w) wave_off += s_wave[k];
+        total += s_wave[k];
+    }
+    int excl = wave_off + x - sum;
+    if (threadIdx.x == 0) {
+        int prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&status[0], kScanInc | (uint32_t)total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&status[tile], kScanAgg | (uint32_t)total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            int k = tile - 1, spins = 0;
+            while (k >= 0) {
+                uint64_t st = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t flag = st & (3ull << 62);
+                if (flag == 0ull) {
+                    if (++spins > (1 << 26)) {
+                        atomicMin(err, err_key(0, -10));
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += (int)(uint32_t)st;
+                if (flag == kScanInc) break;
+                --k;
+            }
+            __hip_atomic_store(&status[tile], kScanInc | (uint32_t)(prefix + total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_prefix = prefix;
+    }
+    __syncthreads();
+    int run = s_prefix + excl;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        if (i0 + j < n) out[i0 + j] = run;
+        run += v[j];
+    }
+    const int last_tile = (n + kScanBlock * kScanItems - 1) / (kScanBlock * kScanItems) - 1;
+    if (tile == (last_tile < 0 ? 0 : last_tile) && threadIdx.x == kScanBlock - 1) out[n] = run;
+}
+
+__global__ void k_bucket(const int32_t *__restrict__ org, int nh, const int32_t *__restrict__ vstart,
+                         int32_t *fill, int32_t *bucket) {
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+        int v = org[h];
+        int slot = vstart[v] + atomicAdd(&fill[v], 1);
+        bucket[slot] = h;
+    }
+}
+
+__global__ void k_match(const int32_t *__restrict__ org, int nt, const int32_t *__restrict__ vstart,
+                        const int32_t *__restrict__ bucket, int32_t *__restrict__ twin,
+                        unsigned long long *err) {
+    const int nh = 3 * nt;
+    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
+        int u = org[h], v = org[he_next_b(h)];
+        int found = -1, nrev = 0, ndup = 0;
+        for (int k = vstart[v], e = vstart[v + 1]; k < e; k++) {
+            int g = bucket[k];
+            if (org[he_next_b(g)] == u) {
+                found = g;
+                ++nrev;
+            }
+        }
+        for (int k = vstart[u], e = vstart[u + 1]; k < e; k++) {
+            int g = bucket[k];
+            if (g != h && org[he_next_b(g)] == v) ++ndup;
+        }
+        if (nrev > 1 || ndup > 0) atomicMin(err, err_key(1ull + nt + h, -4));
+        twin[h] = nrev == 1 ? found : -1;
+    }
+}
+
+inline int grid_for(long long n, int block, int cap = 1 << 16) {
+    long long g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+}  // namespace
+
+int32_t build_scan_tiles(int32_t n) {
+    int per = kScanBlock * kScanItems;
+    int k = (n + per - 1) / per;
+    return k < 1 ? 1 : k;
+}
+
+hipError_t launch_build_orient(const BuildBuffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_xy, dim3(grid_for(b.nv, 256)), dim3(256), 0, s, b.xy, b.nv, b.err_key);
+    if (b.nt > 0)
+        hipLaunchKernelGGL(k_orient, dim3(grid_for(b.nt, 256)), dim3(256), 0, s, b.xy, b.tri, b.nv, b.nt,
+                           b.org, b.deg, b.err_key, b.nflipped);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s) {
+    int tiles = build_scan_tiles(b.nv);
+    hipLaunchKernelGGL(k_scan_excl, dim3(tiles), dim3(kScanBlock), 0, s, b.deg, b.vstart, b.nv,
+                       b.scan_status, b.scan_ctr, b.err_key);
+    long long nh = 3ll * b.nt;
+    if (nh > 0) {
+        hipLaunchKernelGGL(k_bucket, dim3(grid_for(nh, 256)), dim3(256), 0, s, b.org, (int)nh, b.vstart,
+                           b.fill, b.bucket);
+        hipLaunchKernelGGL(k_match, dim3(grid_for(nh, 256)), dim3(256), 0, s, b.org, b.nt, b.vstart,
+                           b.bucket, b.twin, b.err_key);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gp

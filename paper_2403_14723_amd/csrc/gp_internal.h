@@ -1,0 +1,135 @@
+// Internal types shared by the gpolylla kernels and the host runtime.
+//
+// Device data layout (one mesh; all int32 unless noted; h = 3t+i):
+//   xy[2V]      interleaved coordinates, read as int2 (one 8-byte gather)
+//   org[3T]     origin vertex of each half-edge (counter-clockwise corners)
+//   twin[3T]    opposite half-edge, -1 on the boundary
+//   tflag[T]    uint8 per triangle: bits 0-1 local index of the longest edge,
+//               bits 2-4 "added by the repair" for local edges 0..2
+//   pl[T]       uint8 per triangle: 0, or (min(L,63) << 2 | i) when half-edge
+//               3t+i is the minimum of a loop of length L
+//   next_o/prev_o[3T], seeds[<=T], loop_off[<=T+1], loop_he[<=3T] (outputs)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gp {
+
+constexpr int kWave = 64;
+constexpr int kPlMax = 63;            // loop lengths >= 63 are re-counted when emitted
+constexpr int kRotGuard = 1 << 20;    // bound on turns around one vertex
+
+// error bits collected on the device
+constexpr int kErrCorrupt = 1;
+
+// per-mesh counters, written by the kernels and read back once per run
+struct MeshCounters {
+    int32_t err;
+    int32_t nterm;
+    int32_t ntips;
+    int32_t nmiddle;
+    int32_t nties;
+    int32_t npoly;
+    int32_t nloop;
+    int32_t pad;
+};
+
+// list sizes and the dynamic tile counter of one run
+struct RunCounters {
+    int32_t ntips;
+    int32_t ncand;
+    int32_t nfix;
+    int32_t tile_ctr;
+    int32_t err;
+    int32_t pad[3];
+};
+
+struct MeshDesc {
+    const int2 *xy;
+    const int32_t *org;
+    const int32_t *twin;
+    int32_t *next_o;
+    int32_t *prev_o;
+    uint8_t *tflag;
+    uint8_t *pl;
+    int32_t *seeds;
+    int32_t *loop_off;
+    int32_t *loop_he;
+    MeshCounters *ctr;
+    int32_t nt;
+    int32_t nv;
+    int32_t tri_tile0;   // first tile of this mesh in the triangle tile space
+    int32_t he_tile0;    // first tile of this mesh in the half-edge tile space
+    int32_t cmp_tile0;   // first tile of this mesh in the compaction tile space
+    int32_t pad;
+};
+
+struct ListEntry {
+    int32_t mesh;
+    int32_t he;
+};
+
+// ---- launch plumbing (host side, defined in mesh_kernels.hip) ------------
+
+struct LaunchCfg {
+    int block_label = 256, items_label = 4;
+    int block_relink = 256, items_relink = 2;
+    int block_compact = 256, items_compact = 8;
+    int persistent_blocks = 1024;
+    int block_persistent = 256;
+};
+
+struct RunBuffers {
+    const MeshDesc *descs;   // device, nmesh entries
+    int nmesh;
+    int32_t tri_tiles;       // total triangle tiles (label)
+    int32_t he_tiles;        // total half-edge tiles (relink)
+    int32_t cmp_tiles;       // total compaction tiles
+    RunCounters *rc;         // device
+    ListEntry *tips;         // capacity cap_tips
+    ListEntry *cands;        // capacity cap_cands
+    ListEntry *fixes;        // capacity cap_fix
+    int32_t cap_tips, cap_cands, cap_fix;
+    uint64_t *status;        // compaction tile status, cmp_tiles entries
+    MeshCounters *ctrs;      // device, nmesh entries
+};
+
+enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_COUNT };
+extern const char *const kKernelNames[K_COUNT];
+
+// Per-kernel hooks so the runtime can bracket launches with events.
+typedef void (*launch_hook)(void *user, int kernel_id, int after);
+
+hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s,
+                           launch_hook hook, void *user);
+
+// tiles of one mesh for a given tile size; every mesh has at least one tile
+// so that an empty mesh still gets its loop_off[0] written
+inline int32_t tiles_for(int64_t n, int64_t tile) {
+    int64_t k = (n + tile - 1) / tile;
+    return (int32_t)(k < 1 ? 1 : k);
+}
+
+// ---- build (build_kernels.hip) -------------------------------------------
+
+struct BuildBuffers {
+    const int2 *xy;
+    const int32_t *tri;
+    int32_t nv, nt;
+    int32_t *org, *twin;
+    int32_t *deg;      // nv + 1, zeroed by the build
+    int32_t *vstart;   // nv + 1
+    int32_t *fill;     // nv
+    int32_t *bucket;   // 3 nt
+    uint64_t *scan_status;  // scan tiles
+    int32_t *scan_ctr;
+    unsigned long long *err_key;  // lowest (rank << 8 | code) seen
+    int32_t *nflipped;
+};
+
+hipError_t launch_build_orient(const BuildBuffers &b, hipStream_t s);
+hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s);
+int32_t build_scan_tiles(int32_t n);
+
+}  // namespace gp

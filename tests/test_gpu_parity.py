@@ -1,0 +1,221 @@
+"""GPU parity: the HIP path, called through the C ABI, against the oracle.
+
+Every output array is compared element by element (integer work: bit-exact)
+on the same seeded inputs: hand-made fixtures, small jittered / warped grids,
+Delaunay meshes of random points (many barrier tips), the paper's clockwise
+grid, the 32x32 and 1024x1024 workloads, and the 4096x4096 warped workload at
+full size in the launch configuration the benchmark uses.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_14723_amd as gp
+from paper_2403_14723_amd import workloads as W
+from tests import polycheck as pc
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gp.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, xy, tri, name=""):
+    say(f"[gpu] {name}: nv={len(xy)} nt={len(tri)}")
+    m = ctx.build_halfedges(xy, tri)
+    org, twin, nflip = m.copy()
+    r = ctx.mesh(m)
+    out = r.copy()
+    r.free()
+    m.free()
+    out.update(org=org, twin=twin, nflipped=nflip)
+    return out
+
+
+def assert_parity(g, o, name=""):
+    for key, a, b in (("org", g["org"], o.org), ("twin", g["twin"], o.twin), ("next", g["next"], o.next),
+                      ("prev", g["prev"], o.prev), ("seeds", g["seeds"], o.seeds),
+                      ("loop_off", g["loop_off"], o.loop_off), ("loop_he", g["loop_he"], o.loop_he)):
+        assert a.shape == b.shape, f"{name}: {key} shape {a.shape} vs {b.shape}"
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"{name}: {key} differs at {len(bad)} positions, first {bad[:5]}: "
+                                 f"gpu {a[bad[:5]]} oracle {b[bad[:5]]}")
+    info = g["info"]
+    for k in ("npoly", "nloop_he", "nterminal", "ntips", "nmiddle", "nties"):
+        assert info[k] == o.stats[k], f"{name}: {k} gpu {info[k]} oracle {o.stats[k]}"
+    assert g["nflipped"] == o.stats["nflipped"]
+
+
+def check_case(ctx, xy, tri, name):
+    o = oracle.polylla(xy, tri)
+    g = run_gpu(ctx, xy, tri, name)
+    assert_parity(g, o, name)
+    return g, o
+
+
+FIXTURES = ["p1_two_triangles_square.txt", "p2_one_triangle.txt", "p3_fan_degree8.txt",
+            "p4_fan_degree7.txt", "p_tie_break.txt"]
+
+
+@pytest.mark.parametrize("name", FIXTURES)
+def test_fixtures(ctx, name):
+    fx = pc.load_fixture(name)
+    check_case(ctx, fx["xy"], fx["tri"], name)
+
+
+def _small_cases():
+    out = []
+    for n in (1, 2, 3, 7, 16, 33, 64):
+        for seed in range(3):
+            out.append(W.jittered_grid(n, seed=seed))
+    for n, seed in ((24, 100), (40, 101), (96, 102)):
+        out.append(W.jittered_grid(n, seed=seed, warp=True))
+    for n in (5, 12):
+        out.append(W.jittered_grid(n, seed=7, jitter=0.0))
+    for npts, seed in ((10, 1), (300, 2), (5000, 3), (60000, 4)):
+        out.append(W.random_delaunay(npts, seed))
+    return out
+
+
+SMALL = _small_cases()
+
+
+@pytest.mark.parametrize("mesh", SMALL, ids=[m.name for m in SMALL])
+def test_small(ctx, mesh):
+    check_case(ctx, mesh.xy, mesh.tri, mesh.name)
+
+
+def test_paper_grid_clockwise(ctx):
+    xy, tri = pc.paper_grid(2500)
+    g, o = check_case(ctx, xy, tri, "paper_grid_2500")
+    assert g["nflipped"] == len(tri)
+
+
+def test_plain_small_workload(ctx):
+    m = W.plain_small()
+    g, o = check_case(ctx, m.xy, m.tri, m.name)
+    pc.check_output(m.xy, g["org"], g["twin"], g["next"], g["prev"], g["seeds"], g["loop_off"],
+                    g["loop_he"])
+
+
+def test_plain_scale_workload(ctx):
+    m = W.plain_scale()
+    check_case(ctx, m.xy, m.tri, m.name)
+
+
+def test_delaunay_large(ctx):
+    m = W.random_delaunay(400000, 11)
+    g, o = check_case(ctx, m.xy, m.tri, m.name)
+    assert o.stats["ntips"] > 1000
+
+
+def test_plain_large_warped_full(ctx):
+    """The 33.5M-triangle workload at full size, default launch configuration
+    (the one the benchmark times), every output element compared."""
+    m = W.plain_large_warped()
+    g, o = check_case(ctx, m.xy, m.tri, m.name)
+    assert o.stats["ntips"] > 0
+
+
+def test_batch_equals_plain(ctx):
+    meshes = [W.jittered_grid(s, seed=900 + k, warp=(k % 3 == 0)) for k, s in
+              enumerate([16, 1, 40, 23, 64, 5, 100, 37])] + [W.random_delaunay(3000, 77)]
+    hs = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
+    say(f"[gpu] batch of {len(hs)}")
+    rs = ctx.mesh_batch(hs)
+    for m, h, r in zip(meshes, hs, rs):
+        got = r.copy()
+        o = oracle.polylla(m.xy, m.tri)
+        org, twin, nflip = h.copy()
+        got.update(org=org, twin=twin, nflipped=nflip)
+        assert_parity(got, o, "batch:" + m.name)
+        r.free()
+    # a mesh may appear twice in one batch
+    rs = ctx.mesh_batch([hs[2], hs[2]])
+    a, b = rs[0].copy(), rs[1].copy()
+    for k in ("next", "prev", "seeds", "loop_off", "loop_he"):
+        assert np.array_equal(a[k], b[k])
+    for r in rs:
+        r.free()
+    for h in hs:
+        h.free()
+
+
+@pytest.mark.parametrize("block,items", [(64, 1), (128, 2), (512, 8), (1024, 4)])
+def test_launch_shapes_do_not_change_results(block, items):
+    m = W.jittered_grid(150, seed=31, warp=True)
+    o = oracle.polylla(m.xy, m.tri)
+    with gp.Context(0, block=block, items=items) as c:
+        g = run_gpu(c, m.xy, m.tri, f"{m.name} block={block} items={items}")
+    assert_parity(g, o, f"block={block},items={items}")
+
+
+def test_repeat_and_async_identical(ctx):
+    m = W.random_delaunay(20000, 5)
+    h = ctx.build_halfedges(m.xy, m.tri)
+    say("[gpu] repeat/async")
+    rs = [ctx.mesh(h, gp.GP_ASYNC) for _ in range(4)]
+    outs = [r.copy() for r in rs]
+    for r in rs:
+        r.free()
+    for k in ("next", "prev", "seeds", "loop_off", "loop_he"):
+        for o in outs[1:]:
+            assert np.array_equal(outs[0][k], o[k])
+    h.free()
+
+
+def test_device_inputs_from_torch(ctx):
+    import torch
+    m = W.jittered_grid(50, seed=3)
+    xy = torch.from_numpy(m.xy).cuda()
+    tri = torch.from_numpy(m.tri).cuda()
+    torch.cuda.synchronize()
+    say("[gpu] torch device inputs")
+    h = ctx.build_halfedges(xy, tri)
+    r = ctx.mesh(h)
+    g = r.copy()
+    org, twin, nflip = h.copy()
+    g.update(org=org, twin=twin, nflipped=nflip)
+    assert_parity(g, oracle.polylla(m.xy, m.tri), "torch-input")
+    r.free()
+    h.free()
+
+
+def test_empty_mesh(ctx):
+    say("[gpu] empty")
+    h = ctx.build_halfedges(np.zeros((0, 2), np.int32), np.zeros((0, 3), np.int32))
+    r = ctx.mesh(h)
+    g = r.copy()
+    assert g["info"]["npoly"] == 0 and list(g["loop_off"]) == [0]
+    r.free()
+    h.free()
+
+
+@pytest.mark.parametrize("case", ["nonmanifold", "duplicate", "zero_area", "index", "coord"])
+def test_build_errors_match_oracle(ctx, case):
+    xy, tri = {
+        "nonmanifold": ([[0, 10], [10, 10], [5, 15], [5, 5], [5, 19]], [[0, 1, 2], [1, 0, 3], [0, 1, 4]]),
+        "duplicate": ([[0, 0], [10, 0], [5, 5]], [[0, 1, 2], [0, 1, 2]]),
+        "zero_area": ([[0, 0], [1, 1], [2, 2]], [[0, 1, 2]]),
+        "index": ([[0, 0], [1, 0], [0, 1]], [[0, 1, 3]]),
+        "coord": ([[0, 0], [(1 << 30) + 1, 0], [0, 1]], [[0, 1, 2]]),
+    }[case]
+    xy, tri = np.array(xy, np.int32), np.array(tri, np.int32)
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.polylla(xy, tri)
+    say(f"[gpu] build error {case}")
+    with pytest.raises(gp.GPolyllaError) as eg:
+        ctx.build_halfedges(xy, tri)
+    assert eg.value.code == eo.value.code
