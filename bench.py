@@ -41,12 +41,14 @@ def algorithmic_bytes(nt, nv, npoly, nloop):
 
 
 def kernel_bytes(name, nt, nv, npoly, nloop):
-    """Algorithmic bytes of one launch of each kernel."""
+    """Algorithmic bytes of one launch of the streaming kernels.
+    The list-driven kernels (k_repair, k_fixup, k_walk, k_emit) touch only the
+    few loops and vertices on their lists and are not roofline candidates."""
     return {
         "k_label": 12 * nt + 8 * nv + 2 * nt,                 # org, xy -> tflag, pl
+        "k_frontier": 12 * nt + 2 * nt,                       # twin, tflag -> tflag
         "k_relink": 12 * nt + nt + 24 * nt,                   # twin, tflag -> next, prev
-        "k_walk": nt + 4 * nloop + npoly,                     # tflag, next along loops -> pl
-        "k_compact": nt + 4 * nloop + 8 * npoly + 4 * nloop,  # pl, next -> seeds, loop_off, loop_he
+        "k_compact": 2 * nt + 8 * npoly + 4 * nloop,          # pl, tflag -> seeds, loop_off, loop_he
     }.get(name)
 
 

@@ -64,6 +64,10 @@ extern "C" {
 #define GP_IN_DEVICE 0x1u     /* build: xy and tri are device pointers on the context's device */
 #define GP_ASYNC 0x2u         /* mesh: return once the work is queued; counts are read
                                  (and errors reported) by the first result query */
+#define GP_GRAPH 0x4u         /* mesh: replay a captured hipGraph of the kernel chain; the
+                                 graph is captured on the first call for a batch shape (the
+                                 list of triangle counts) and reused while the shape repeats
+                                 (up to 4 shapes per context; ignored when profiling) */
 #define GP_OUT_LOOPS 0x10u    /* mesh: also produce seeds / loop_off / loop_he (default on) */
 #define GP_OUT_NO_LOOPS 0x20u /* mesh: only next/prev and the counts */
 
@@ -166,6 +170,49 @@ void gpolylla_result_free(gp_result *res);
 
 /* Waits until all queued work of the context has finished. */
 int gpolylla_ctx_sync(gp_ctx *ctx);
+
+/* ---- serving ------------------------------------------------------------ */
+
+typedef struct {
+    size_t pool_bytes;   /* device bytes for requests in flight, split over the lanes; 0 = 16 GiB */
+    int32_t max_batch;   /* requests per batched run; 0 = 64 */
+    int32_t max_queue;   /* queued requests before GP_EAGAIN; 0 = 4096 */
+    int32_t n_lanes;     /* streams whose batches overlap on the device (1..8); 0 = 2 */
+} gp_serve_opts;
+
+typedef struct {
+    int64_t submitted, completed, rejected, failed, batches, in_flight;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> result on the host */
+    double mtri_s;                            /* triangles completed per second, first submit to last result */
+} gp_serve_stats;
+
+/*
+ * Starts a server on the device of ctx (whose launch shapes it copies).  The
+ * server owns its own streams and device memory: n_lanes arenas of
+ * pool_bytes / n_lanes each.  A request is admitted into a batch when the
+ * exact device footprint of the batch (every half-edge build plus the
+ * batched meshing run) fits a lane's arena.  Batches on different lanes
+ * overlap; requests that arrive while batches run join the next free lane
+ * (continuous batching).  ctx itself is not used after the call.
+ */
+int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out);
+/* Queues a triangulation (host arrays, copied before return).  Errors:
+ * GP_EINVAL, GP_ERANGE, GP_ETOOBIG (footprint above one lane's arena),
+ * GP_EAGAIN (queue full).  Thread-safe. */
+int gpolylla_serve_submit(gp_server *srv, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
+                          uint64_t *ticket);
+/* Waits for a ticket (timeout_ms < 0: forever).  On success *out is a
+ * host-resident result (gpolylla_result_info / _copy / _free work on it;
+ * gpolylla_result_device does not).  Returns the request's status (its build
+ * or meshing error), GP_ETIMEDOUT, or GP_EINVAL for an unknown ticket.  A
+ * ticket can be waited for once.  Thread-safe. */
+int gpolylla_serve_wait(gp_server *srv, uint64_t ticket, int32_t timeout_ms, gp_result **out);
+int gpolylla_serve_stats(gp_server *srv, gp_serve_stats *stats);
+/* Clears the latency and throughput statistics (after a warm-up). */
+int gpolylla_serve_reset_stats(gp_server *srv);
+/* Finishes every queued request, then stops.  Results already handed out
+ * stay valid until freed. */
+int gpolylla_serve_stop(gp_server *srv);
 
 const char *gpolylla_strerror(int code);
 

@@ -24,6 +24,7 @@ GP_EINVAL, GP_ERANGE, GP_EDEGEN, GP_ENONMANIFOLD, GP_ENOMEM, GP_EHIP = -1, -2, -
 GP_EAGAIN, GP_ETOOBIG, GP_ETIMEDOUT, GP_ECORRUPT = -7, -8, -9, -10
 GP_IN_DEVICE = 0x1
 GP_ASYNC = 0x2
+GP_GRAPH = 0x4
 GP_OUT_LOOPS = 0x10
 GP_OUT_NO_LOOPS = 0x20
 
@@ -43,6 +44,17 @@ class gp_ctx_opts(ctypes.Structure):
 class gp_result_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("nt", "nv", "nh", "npoly", "nloop_he", "nterminal",
                                               "ntips", "nmiddle", "nties", "nflipped")]
+
+
+class gp_serve_opts(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("n_lanes", ctypes.c_int32)]
+
+
+class gp_serve_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "failed", "batches",
+                                              "in_flight")] + \
+               [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "mtri_s")]
 
 
 class gp_result_dev(ctypes.Structure):
@@ -92,6 +104,13 @@ def _load():
         "gpolylla_result_copy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
         "gpolylla_result_device": (ctypes.c_int, [_P, ctypes.POINTER(gp_result_dev)]),
         "gpolylla_result_free": (None, [_P]),
+        "gpolylla_serve_start": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_opts), ctypes.POINTER(_P)]),
+        "gpolylla_serve_submit": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_uint64)]),
+        "gpolylla_serve_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(_P)]),
+        "gpolylla_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_stats)]),
+        "gpolylla_serve_reset_stats": (ctypes.c_int, [_P]),
+        "gpolylla_serve_stop": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -114,7 +133,8 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_ctx_sync", "gpolylla_ctx_kernel_ms", "gpolylla_ctx_kernel_reset",
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
-            "gpolylla_result_device", "gpolylla_result_free"]
+            "gpolylla_result_device", "gpolylla_result_free", "gpolylla_serve_start", "gpolylla_serve_submit",
+            "gpolylla_serve_wait", "gpolylla_serve_stats", "gpolylla_serve_reset_stats", "gpolylla_serve_stop"]
 
 
 def _check(rc: int, what: str):
@@ -248,6 +268,42 @@ def gpolylla_result_free(res):
     _load().gpolylla_result_free(res)
 
 
+def gpolylla_serve_start(ctx, opts: gp_serve_opts | None = None):
+    out = _P()
+    _check(_load().gpolylla_serve_start(ctx, ctypes.byref(opts) if opts else None, ctypes.byref(out)),
+           "gpolylla_serve_start")
+    return out
+
+
+def gpolylla_serve_submit(srv, xy, tri) -> int:
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
+    tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1, 3))
+    t = ctypes.c_uint64()
+    _check(_load().gpolylla_serve_submit(srv, xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
+                                         ctypes.byref(t)), "gpolylla_serve_submit")
+    return int(t.value)
+
+
+def gpolylla_serve_wait(srv, ticket: int, timeout_ms: int = -1):
+    out = _P()
+    _check(_load().gpolylla_serve_wait(srv, ticket, timeout_ms, ctypes.byref(out)), "gpolylla_serve_wait")
+    return out
+
+
+def gpolylla_serve_stats(srv) -> dict:
+    st = gp_serve_stats()
+    _check(_load().gpolylla_serve_stats(srv, ctypes.byref(st)), "gpolylla_serve_stats")
+    return {n: getattr(st, n) for n, _ in gp_serve_stats._fields_}
+
+
+def gpolylla_serve_reset_stats(srv):
+    _check(_load().gpolylla_serve_reset_stats(srv), "gpolylla_serve_reset_stats")
+
+
+def gpolylla_serve_stop(srv):
+    _check(_load().gpolylla_serve_stop(srv), "gpolylla_serve_stop")
+
+
 # ---------------------------------------------------------------------------
 # wrappers
 # ---------------------------------------------------------------------------
@@ -296,6 +352,38 @@ class Result:
                 self.free()
         except Exception:
             pass
+
+
+class Server:
+    """Continuous-batching server (see gpolylla_serve_start)."""
+
+    def __init__(self, ctx: "Context", pool_bytes: int = 0, max_batch: int = 0, max_queue: int = 0,
+                 n_lanes: int = 0):
+        self.handle = gpolylla_serve_start(ctx.handle, gp_serve_opts(pool_bytes, max_batch, max_queue, n_lanes))
+        self._ctx = ctx
+
+    def submit(self, xy, tri) -> int:
+        return gpolylla_serve_submit(self.handle, xy, tri)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> Result:
+        return Result(self._ctx, gpolylla_serve_wait(self.handle, ticket, timeout_ms))
+
+    def stats(self) -> dict:
+        return gpolylla_serve_stats(self.handle)
+
+    def reset_stats(self):
+        gpolylla_serve_reset_stats(self.handle)
+
+    def stop(self):
+        if self.handle:
+            gpolylla_serve_stop(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.stop()
 
 
 class Context:

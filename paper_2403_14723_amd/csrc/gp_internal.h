@@ -5,7 +5,7 @@
 //   org[3T]     origin vertex of each half-edge (counter-clockwise corners)
 //   twin[3T]    opposite half-edge, -1 on the boundary
 //   tflag[T]    uint8 per triangle: bits 0-1 local index of the longest edge,
-//               bits 2-4 "added by the repair" for local edges 0..2
+//               bits 2-4 frontier bit of local edges 0..2, bit 5 seed
 //   pl[T]       uint8 per triangle: 0, or (min(L,63) << 2 | i) when half-edge
 //               3t+i is the minimum of a loop of length L
 //   next_o/prev_o[3T], seeds[<=T], loop_off[<=T+1], loop_he[<=3T] (outputs)
@@ -38,7 +38,7 @@ struct MeshCounters {
 // list sizes and the dynamic tile counter of one run
 struct RunCounters {
     int32_t ntips;
-    int32_t ncand;
+    int32_t unused;
     int32_t nfix;
     int32_t tile_ctr;
     int32_t err;
@@ -60,7 +60,7 @@ struct MeshDesc {
     int32_t nt;
     int32_t nv;
     int32_t tri_tile0;   // first tile of this mesh in the triangle tile space
-    int32_t he_tile0;    // first tile of this mesh in the half-edge tile space
+    int32_t he_tile0;    // first tile of this mesh in the relink tile space (triangles)
     int32_t cmp_tile0;   // first tile of this mesh in the compaction tile space
     int32_t pad;
 };
@@ -70,12 +70,25 @@ struct ListEntry {
     int32_t he;
 };
 
+// a loop whose half-edges k_emit writes: minimum mn, first output slot off
+struct EmitEntry {
+    int32_t mesh;
+    int32_t mn;
+    int32_t off;
+};
+
+// Lists appended to by many workgroups are split into kStripes stripes, each
+// with its own counter, so appends do not all hit one address.  Stripe s
+// holds entries [s*cap, s*cap + min(count[s], cap)).
+constexpr int kStripes = 64;
+constexpr int kStripePad = 32;   // counters 128 bytes apart: one cache line each
+
 // ---- launch plumbing (host side, defined in mesh_kernels.hip) ------------
 
 struct LaunchCfg {
     int block_label = 256, items_label = 4;
-    int block_relink = 256, items_relink = 2;
-    int block_compact = 256, items_compact = 8;
+    int block_relink = 256, items_relink = 2;     // k_frontier and k_relink (tile <= 1024 triangles)
+    int block_compact = 512, items_compact = 4;   // tile <= 2048 triangles (LDS 20 B each)
     int persistent_blocks = 1024;
     int block_persistent = 256;
 };
@@ -84,18 +97,23 @@ struct RunBuffers {
     const MeshDesc *descs;   // device, nmesh entries
     int nmesh;
     int32_t tri_tiles;       // total triangle tiles (label)
-    int32_t he_tiles;        // total half-edge tiles (relink)
+    int32_t he_tiles;        // total relink tiles
     int32_t cmp_tiles;       // total compaction tiles
     RunCounters *rc;         // device
     ListEntry *tips;         // capacity cap_tips
-    ListEntry *cands;        // capacity cap_cands
     ListEntry *fixes;        // capacity cap_fix
-    int32_t cap_tips, cap_cands, cap_fix;
+    int32_t cap_tips, cap_fix;
     uint64_t *status;        // compaction tile status, cmp_tiles entries
     MeshCounters *ctrs;      // device, nmesh entries
+    ListEntry *walk;         // striped: seeds left open by k_relink and repair seeds
+    int32_t *walk_counts;    // kStripes counters, kStripePad ints apart
+    int32_t walk_cap;        // per stripe
+    EmitEntry *emit;         // striped: loops k_compact leaves to k_emit
+    int32_t *emit_counts;    // kStripes counters, kStripePad ints apart
+    int32_t emit_cap;        // per stripe
 };
 
-enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_COUNT };
+enum KernelId { K_INIT = 0, K_LABEL, K_FRONTIER, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.

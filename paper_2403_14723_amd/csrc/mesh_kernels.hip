@@ -2,32 +2,44 @@
 //
 // One run processes a batch of meshes through a per-mesh descriptor table
 // (a plain call is a batch of one).  Streaming kernels tile each mesh
-// separately, so a workgroup never straddles two meshes and all indices it
-// handles are local to one mesh; data-dependent work (tips, repair seeds,
-// fix-ups) goes through small device lists read by persistent grids.
+// separately, so a workgroup never straddles two meshes and every index it
+// handles is local to one mesh; data-dependent work (barrier tips, repair
+// seeds, fix-ups) goes through small device lists read by persistent grids.
 //
-// Kernel chain (paper Section 6, Algorithm 7, restructured):
-//   k_init     clears run counters, per-mesh counters and scan tile status
-//   k_label    longest edge per triangle (Section 6.1, Algorithm 8)
-//   k_relink   frontier test (Section 6.2, Algorithm 9), terminal-edge seeds
-//              (Section 6.3, Algorithm 10) and next/prev of every frontier
-//              half-edge by turning around its target / origin (Section 6.5,
-//              Algorithm 12); records barrier tips
-//   k_repair   middle edge at each barrier tip (Section 6.4, Algorithm 11)
-//   k_fixup    recomputes next/prev around the endpoints of new frontier edges
-//   k_walk     from every seed: move to a frontier half-edge (Section 6.5.1,
-//              Algorithm 13), walk its loop, record minimum and length at the
-//              minimum's triangle (Section 6.6, Algorithm 14)
-//   k_walk_rep the same for the seeds made by the repair
-//   k_compact  scan of loop minima and lengths with decoupled look-back,
-//              writing seeds, loop offsets and the loops themselves
-//              (Section 6.7)
+// Kernel chain (the eight kernels of the paper's Section 6 / Algorithm 7,
+// regrouped so that every step reads its inputs contiguously):
+//   k_init      clears run counters, per-mesh counters and scan tile status
+//   k_label     longest edge of every triangle (Section 6.1, Algorithm 8)
+//   k_frontier  frontier bits of every half-edge (Section 6.2, Algorithm 9)
+//               and the seed bit of terminal edges (Section 6.3, Algorithm 10)
+//   k_relink    next/prev of every frontier half-edge by turning around its
+//               target / origin (Section 6.5, Algorithm 12); barrier tips
+//   k_repair    middle edge at every barrier tip (Section 6.4, Algorithm 11)
+//   k_fixup     next/prev again around both ends of every new frontier edge
+//   k_walk      for every seed k_relink left open and every seed made by the
+//               repair: move to a frontier half-edge of its polygon
+//               (Section 6.5.1, Algorithm 13), walk the loop, and record its
+//               minimum and length at the minimum's triangle (Section 6.6,
+//               Algorithm 14).  Polygons of one or two triangles are settled
+//               by k_relink itself.
+//   k_compact   scan of loop minima and lengths (decoupled look-back) that
+//               writes seeds, loop offsets and the loops of up to four
+//               half-edges (Section 6.7)
+//   k_emit      writes the longer loops at the offsets k_compact reserved
+//
+// Label byte per triangle (tflag):
+//   bits 0-1  local index of the longest edge
+//   bits 2-4  frontier bit of local edges 0..2 (the repair sets more of them)
+//   bit  5    the longest edge is a terminal edge and this triangle holds its
+//             seed half-edge
 #include "gp_internal.h"
 
 namespace gp {
 
-const char *const kKernelNames[K_COUNT] = {"k_init", "k_label", "k_relink", "k_repair",
-                                           "k_fixup", "k_walk", "k_compact"};
+const char *const kKernelNames[K_COUNT] = {"k_init",   "k_label", "k_frontier", "k_relink", "k_repair",
+                                           "k_fixup",  "k_walk",  "k_compact",  "k_emit"};
+
+constexpr uint32_t kSeedBit = 1u << 5;
 
 // ---------------------------------------------------------------------------
 // half-edge queries (implicit triangle layout, Section 4.2)
@@ -47,45 +59,40 @@ __device__ __forceinline__ long long sq_len(int2 a, int2 b) {
     return dx * dx + dy * dy;
 }
 
-// Frontier test after the repair: boundary, longest edge of neither side, or
-// added by the repair.  Before the repair the repair bits are all zero.
-__device__ __forceinline__ bool is_frontier(const int32_t *__restrict__ twin,
-                                            const uint8_t *__restrict__ tflag, int h) {
-    int t = h / 3, i = h - 3 * t;
-    uint32_t f = tflag[t];
-    if ((f >> (2 + i)) & 1u) return true;
-    int g = twin[h];
-    if (g < 0) return true;
-    if ((int)(f & 3u) == i) return false;
-    int tg = g / 3;
-    return (int)(tflag[tg] & 3u) != g - 3 * tg;
+__device__ __forceinline__ bool fbit(uint32_t f, int i) { return (f >> (2 + i)) & 1u; }
+
+__device__ __forceinline__ bool is_frontier(const uint8_t *__restrict__ tflag, int h) {
+    const int t = h / 3;
+    return fbit(tflag[t], h - 3 * t);
 }
 
-// next'(h): first frontier half-edge met turning clockwise around target(h),
-// starting from next(h).  Returns -1 if the guard trips.
-__device__ __forceinline__ int turn_next(const int32_t *__restrict__ twin,
-                                         const uint8_t *__restrict__ tflag, int h) {
-    int n = he_next(h);
+// Turning from candidate c (label fc of its triangle): the first frontier
+// half-edge met.  NEXT: clockwise around the target of the half-edge being
+// linked, c <- next(twin(c)); !NEXT: the mirror, c <- prev(twin(c)).  A
+// non-frontier edge is interior, so twin(c) exists.  -1 when the guard trips.
+template <bool NEXT>
+__device__ __forceinline__ int turn(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag, int c,
+                                    uint32_t fc) {
     for (int k = 0; k < kRotGuard; k++) {
-        if (is_frontier(twin, tflag, n)) return n;
-        int g = twin[n];
+        const int tc = c / 3;
+        if (fbit(fc, c - 3 * tc)) return c;
+        const int g = twin[c];
         if (g < 0) return -1;
-        n = he_next(g);
+        c = NEXT ? he_next(g) : he_prev(g);
+        fc = tflag[c / 3];
     }
     return -1;
 }
 
-// prev'(h): the mirror turn around origin(h), starting from prev(h).
-__device__ __forceinline__ int turn_prev(const int32_t *__restrict__ twin,
-                                         const uint8_t *__restrict__ tflag, int h) {
-    int p = he_prev(h);
-    for (int k = 0; k < kRotGuard; k++) {
-        if (is_frontier(twin, tflag, p)) return p;
-        int g = twin[p];
-        if (g < 0) return -1;
-        p = he_prev(g);
-    }
-    return -1;
+__device__ __forceinline__ int turn_next(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag,
+                                         int h) {
+    const int c = he_next(h);
+    return turn<true>(twin, tflag, c, tflag[c / 3]);
+}
+__device__ __forceinline__ int turn_prev(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag,
+                                         int h) {
+    const int c = he_prev(h);
+    return turn<false>(twin, tflag, c, tflag[c / 3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -117,7 +124,13 @@ __device__ __forceinline__ void wave_incl_scan2(int &a, int &b) {
     }
 }
 
-// Exclusive block scan of a pair; lds must hold 3*16 ints per component.
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// Exclusive block scan of a pair; lds must hold 66 ints.
 __device__ __forceinline__ void block_excl_scan2(int a, int b, int &ea, int &eb, int &ta, int &tb,
                                                  int *lds) {
     int ia = a, ib = b;
@@ -164,17 +177,98 @@ __device__ __forceinline__ int find_mesh(const MeshDesc *__restrict__ d, int n, 
     return lo;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b on XCD b % 8)
+// and each XCD has its own L2.  This gives every XCD one contiguous run of
+// tiles, so the neighbour rows a tile gathers from were mostly touched by the
+// same XCD.  A bijection of [0, G).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Block-wide reservation in stripe `stripe` of a striped list: every thread
+// asks for n entries; one atomic per block.  Returns the thread's first entry
+// index (stripe*cap + slot); slots at or beyond cap are dropped by the caller
+// and reported through *full.  Called by every thread of the block.
+__device__ __forceinline__ int block_reserve(int32_t *counts, int cap, int stripe, int n, int *s_scan,
+                                             int *s_base, bool *full) {
+    int excl, dummy, total, dummy2;
+    block_excl_scan2(n, 0, excl, dummy, total, dummy2, s_scan);
+    if (threadIdx.x == 0) *s_base = total > 0 ? atomicAdd(&counts[stripe * kStripePad], total) : 0;
+    __syncthreads();
+    const int base = *s_base;
+    __syncthreads();
+    if (base + total > cap) *full = true;
+    return stripe * cap + base + excl;
+}
+
+// Prefix sums of the stripe sizes in LDS (s_pref[0..kStripes]); returns the
+// total.  Called by every thread of the block.
+__device__ __forceinline__ int striped_prefix(const int32_t *counts, int cap, int *s_pref) {
+    static_assert(kStripes == kWave, "one lane per stripe");
+    if (threadIdx.x < kWave) {
+        int c = counts[threadIdx.x * kStripePad];
+        c = c < 0 ? 0 : (c > cap ? cap : c);
+        int x = c;
+#pragma unroll
+        for (int dd = 1; dd < kWave; dd <<= 1) {
+            const int y = __shfl_up(x, dd);
+            if ((int)threadIdx.x >= dd) x += y;
+        }
+        s_pref[threadIdx.x + 1] = x;
+        if (threadIdx.x == 0) s_pref[0] = 0;
+    }
+    __syncthreads();
+    return s_pref[kStripes];
+}
+
+// Entry index of the g-th element of a striped list.
+__device__ __forceinline__ int striped_index(const int *s_pref, int cap, int g) {
+    int lo = 0, hi = kStripes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo * cap + (g - s_pref[lo]);
+}
+
+// Copies n ints from global src to LDS dst; src and dst 16-byte aligned.
+__device__ __forceinline__ void load_to_lds(int *dst, const int32_t *__restrict__ src, int n) {
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int4 *s4 = reinterpret_cast<const int4 *>(src);
+    int4 *d4 = reinterpret_cast<int4 *>(dst);
+    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
+    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
+}
+
+// Copies n ints from LDS src to global dst; both 16-byte aligned.
+__device__ __forceinline__ void store_from_lds(int32_t *dst, const int *src, int n) {
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int4 *s4 = reinterpret_cast<const int4 *>(src);
+    int4 *d4 = reinterpret_cast<int4 *>(dst);
+    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
+    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
+}
+
 // ---------------------------------------------------------------------------
 // k_init
 // ---------------------------------------------------------------------------
 
-__global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t *status,
-                       int nstatus) {
+__global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t *status, int nstatus,
+                       int32_t *walk_counts, int32_t *emit_counts) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int stride = gridDim.x * blockDim.x;
+    if (i < kStripes) {
+        walk_counts[i * kStripePad] = 0;
+        emit_counts[i * kStripePad] = 0;
+    }
     if (i == 0) {
         rc->ntips = 0;
-        rc->ncand = 0;
+        rc->unused = 0;
         rc->nfix = 0;
         rc->tile_ctr = 0;
         rc->err = 0;
@@ -191,23 +285,31 @@ __global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t 
 // ---------------------------------------------------------------------------
 
 template <int ITEMS>
-__global__ void k_label(const MeshDesc *__restrict__ descs, int nmesh) {
-    const int tile = blockIdx.x;
+__global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ descs, int nmesh) {
+    extern __shared__ int4 lds_raw[];
+    int *s_org = reinterpret_cast<int *>(lds_raw);
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<0>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
     const int nt = d.nt;
-    const int base = (tile - d.tri_tile0) * (int)blockDim.x * ITEMS;
-    const int32_t *__restrict__ org = d.org;
+    const int base = (tile - d.tri_tile0) * B * ITEMS;
     const int2 *__restrict__ xy = d.xy;
+    // the tile's corners in one contiguous load; item j of this thread is
+    // triangle base + j*B + tid
+    const int cnt_all = min(B * ITEMS, nt - base);
+    if (cnt_all > 0) load_to_lds(s_org, d.org + 3 * (size_t)base, 3 * cnt_all);
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        int t = base + j * (int)blockDim.x + (int)threadIdx.x;
+        const int lt = j * B + tid;
+        const int t = base + lt;
         if (t >= nt) break;
-        int2 p0 = xy[org[3 * t]], p1 = xy[org[3 * t + 1]], p2 = xy[org[3 * t + 2]];
-        long long l0 = sq_len(p0, p1), l1 = sq_len(p1, p2), l2 = sq_len(p2, p0);
+        const int2 p0 = xy[s_org[3 * lt]], p1 = xy[s_org[3 * lt + 1]], p2 = xy[s_org[3 * lt + 2]];
+        const long long l0 = sq_len(p0, p1), l1 = sq_len(p1, p2), l2 = sq_len(p2, p0);
         long long m = l0 > l1 ? l0 : l1;
         m = m > l2 ? m : l2;
-        int cnt = (l0 == m) + (l1 == m) + (l2 == m);
+        const int cnt = (l0 == m) + (l1 == m) + (l2 == m);
         int best;
         if (cnt == 1) {
             best = l0 == m ? 0 : (l1 == m ? 1 : 2);
@@ -215,11 +317,11 @@ __global__ void k_label(const MeshDesc *__restrict__ descs, int nmesh) {
             // tie at the maximum: the lower edge id min(h, twin h) wins
             best = -1;
             int bid = 0x7fffffff;
-            long long ls[3] = {l0, l1, l2};
+            const long long ls[3] = {l0, l1, l2};
             for (int i = 0; i < 3; i++) {
                 if (ls[i] != m) continue;
-                int h = 3 * t + i, g = d.twin[h];
-                int id = (g >= 0 && g < h) ? g : h;
+                const int h = 3 * t + i, g = d.twin[h];
+                const int id = (g >= 0 && g < h) ? g : h;
                 if (id < bid) {
                     bid = id;
                     best = i;
@@ -233,69 +335,197 @@ __global__ void k_label(const MeshDesc *__restrict__ descs, int nmesh) {
 }
 
 // ---------------------------------------------------------------------------
-// k_relink: frontier labels, seeds, next/prev, barrier tips
+// k_frontier: frontier bits and seed bit from the longest-edge labels
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kSeedBit = 1u << 5;   // tflag: the longest edge of t is a terminal seed
-
 template <int ITEMS>
-__global__ void k_relink(const MeshDesc *__restrict__ descs, int nmesh, RunCounters *rc,
-                         ListEntry *tips, int cap_tips) {
-    const int tile = blockIdx.x;
+__global__ void __launch_bounds__(1024) k_frontier(const MeshDesc *__restrict__ descs, int nmesh) {
+    extern __shared__ int4 lds_raw[];
+    int *s_tw = reinterpret_cast<int *>(lds_raw);
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<1>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
-    const int nh = 3 * d.nt;
-    const int base = (tile - d.he_tile0) * (int)blockDim.x * ITEMS;
-    const int32_t *__restrict__ twin = d.twin;
+    const int nt = d.nt;
+    const int base = (tile - d.he_tile0) * B * ITEMS;
+    const int cnt_all = min(B * ITEMS, nt - base);
+    if (cnt_all > 0) load_to_lds(s_tw, d.twin + 3 * (size_t)base, 3 * cnt_all);
+    __syncthreads();
     uint8_t *__restrict__ tflag = d.tflag;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        int h = base + j * (int)blockDim.x + (int)threadIdx.x;
-        bool tip = false;
-        bool err = false;
-        if (h < nh) {
-            int t = h / 3, i = h - 3 * t;
-            uint32_t f = tflag[t];
-            int L = (int)(f & 3u);
-            int g = twin[h];
-            bool g_long = false;
-            if (g >= 0) {
-                int tg = g / 3;
-                g_long = (int)(tflag[tg] & 3u) == g - 3 * tg;
+        const int lt = j * B + tid;
+        const int t = base + lt;
+        if (t >= nt) break;
+        const int tw[3] = {s_tw[3 * lt], s_tw[3 * lt + 1], s_tw[3 * lt + 2]};
+        // only bits 0-1 of the neighbours are read; they do not change here
+        const uint32_t L = tflag[t] & 3u;
+        uint32_t out = L;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            bool twin_long = false;
+            if (tw[i] >= 0) {
+                const int tg = tw[i] / 3;
+                twin_long = (int)(tflag[tg] & 3u) == tw[i] - 3 * tg;
             }
-            bool F = g < 0 || (L != i && !g_long);
-            int n = -1, p = -1;
-            if (F) {
-                n = turn_next(twin, tflag, h);
-                p = turn_prev(twin, tflag, h);
-                err = n < 0 || p < 0;
-                tip = g >= 0 && n == g;
-            }
-            d.next_o[h] = n;
-            d.prev_o[h] = p;
-            // terminal edge: longest on both sides (the lower half-edge is the
-            // seed), or longest and on the boundary
-            if (L == i && (g < 0 || (g_long && h < g))) tflag[t] = (uint8_t)(f | kSeedBit);
+            // frontier: boundary, or the longest edge of neither triangle
+            if (tw[i] < 0 || ((int)L != i && !twin_long)) out |= 1u << (2 + i);
+            // terminal edge: longest on both sides (the lower half-edge holds
+            // the seed), or longest and on the boundary
+            if ((int)L == i && (tw[i] < 0 || (twin_long && 3 * t + i < tw[i]))) out |= kSeedBit;
         }
-        int slot = wave_reserve(&rc->ntips, tip);
+        tflag[t] = (uint8_t)out;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_relink: next/prev of every frontier half-edge, barrier tips
+//
+// One thread per triangle.  Twins are loaded and next/prev stored through
+// LDS so the global accesses are contiguous.  The first candidate of each
+// turn is a half-edge of the same triangle; the second is in the neighbour
+// across the crossed edge, whose label was loaded with the others, so most
+// turns need no load beyond the four labels.
+// ---------------------------------------------------------------------------
+
+// Records loop (minimum mn, length len) in the byte of the minimum's triangle.
+__device__ __forceinline__ void record_loop(const MeshDesc &d, int mn, int len) {
+    const int tm = mn / 3;
+    d.pl[tm] = (uint8_t)(((len < kPlMax ? len : kPlMax) << 2) | (mn - 3 * tm));
+}
+
+template <int ITEMS>
+__global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
+                                                  RunCounters *rc, ListEntry *tips, int cap_tips,
+                                                  ListEntry *walk, int32_t *walk_counts, int walk_cap) {
+    extern __shared__ int4 lds_raw[];
+    int *lds = reinterpret_cast<int *>(lds_raw);
+    const int B = blockDim.x, tid = threadIdx.x, TB = B * ITEMS;
+    int *s_nx = lds, *s_pv = lds + 3 * TB;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int mi = find_mesh<1>(descs, nmesh, tile);
+    const MeshDesc &d = descs[mi];
+    const int nt = d.nt;
+    const int32_t *__restrict__ twin = d.twin;
+    uint8_t *__restrict__ tflag = d.tflag;
+    const int base = (tile - d.he_tile0) * TB;
+    const int cnt = min(TB, nt - base);
+    // every load of every item first (twins, own label, neighbour labels),
+    // so the lane keeps all of them in flight together
+    int tw[ITEMS][3];
+    uint32_t f[ITEMS], fn[ITEMS][3];
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int t = base + j * B + tid;
+        const bool ok = t < nt;
+#pragma unroll
+        for (int i = 0; i < 3; i++) tw[j][i] = ok ? twin[3 * t + i] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int t = base + j * B + tid;
+        f[j] = t < nt ? tflag[t] : 0u;
+#pragma unroll
+        for (int i = 0; i < 3; i++) fn[j][i] = tw[j][i] >= 0 ? tflag[tw[j][i] / 3] : 0u;
+    }
+    bool err = false;
+    int tipmask = 0;    // bit 3*j+i: half-edge i of item j ends at a barrier tip
+    int openmask = 0;   // bit j: item j holds a seed whose loop k_walk must walk
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt >= cnt) continue;
+        const int t = base + lt, h0 = 3 * t;
+        int nx[3] = {-1, -1, -1}, pv[3] = {-1, -1, -1};
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            if (!fbit(f[j], i)) continue;
+            const int jn = i == 2 ? 0 : i + 1, jp = i == 0 ? 2 : i - 1;
+            // a non-frontier edge is interior, so tw[j][jn] / tw[j][jp] >= 0
+            nx[i] = fbit(f[j], jn) ? h0 + jn : turn<true>(twin, tflag, he_next(tw[j][jn]), fn[j][jn]);
+            pv[i] = fbit(f[j], jp) ? h0 + jp : turn<false>(twin, tflag, he_prev(tw[j][jp]), fn[j][jp]);
+            err |= nx[i] < 0 || pv[i] < 0;
+            if (tw[j][i] >= 0 && nx[i] == tw[j][i]) tipmask |= 1 << (3 * j + i);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            s_nx[3 * lt + i] = nx[i];
+            s_pv[3 * lt + i] = pv[i];
+        }
+        // A seed whose polygon is one triangle (boundary terminal edge, both
+        // other edges frontier) or two (interior terminal edge, the four
+        // other edges frontier) is settled here: its loop is those 3 or 4
+        // half-edges.  Such polygons have no interior vertex, so no barrier
+        // tip and no repair touches them.
+        if (f[j] & kSeedBit) {
+            const int L = (int)(f[j] & 3u), a = L == 2 ? 0 : L + 1, b = L == 0 ? 2 : L - 1;
+            bool settled = false;
+            if (fbit(f[j], a) && fbit(f[j], b)) {
+                const int g = tw[j][L];
+                if (g < 0) {
+                    record_loop(d, h0, 3);
+                    settled = true;
+                } else {
+                    const int tp = g / 3, Lp = g - 3 * tp;
+                    const int ap = Lp == 2 ? 0 : Lp + 1, bp = Lp == 0 ? 2 : Lp - 1;
+                    if (fbit(fn[j][L], ap) && fbit(fn[j][L], bp)) {
+                        const int mn = tp < t ? 3 * tp + min(ap, bp) : h0 + min(a, b);
+                        record_loop(d, mn, 4);
+                        settled = true;
+                    }
+                }
+            }
+            if (!settled) openmask |= 1 << j;
+        }
+    }
+    // open seeds go to the walk list (stripe by tile, one atomic per block)
+    {
+        __shared__ int s_scan[72];
+        __shared__ int s_base;
+        bool full = false;
+        int e = block_reserve(walk_counts, walk_cap, tile % kStripes, __popc(openmask), s_scan, &s_base, &full);
+        const int lim = (tile % kStripes + 1) * walk_cap;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            if (!((openmask >> j) & 1)) continue;
+            if (e < lim) {
+                const int t = base + j * B + tid;
+                walk[e].mesh = mi;
+                walk[e].he = 3 * t + (int)(f[j] & 3u);
+            }
+            ++e;
+        }
+        err |= full;
+    }
+    __syncthreads();
+    if (cnt > 0) {
+        store_from_lds(d.next_o + 3 * (size_t)base, s_nx, 3 * cnt);
+        store_from_lds(d.prev_o + 3 * (size_t)base, s_pv, 3 * cnt);
+    }
+    // barrier tips (rare): one list append per wave and slot
+#pragma unroll
+    for (int k = 0; k < 3 * ITEMS; k++) {
+        const bool tip = (tipmask >> k) & 1;
+        const int slot = wave_reserve(&rc->ntips, tip);
         if (tip) {
             if (slot < cap_tips) {
                 tips[slot].mesh = mi;
-                tips[slot].he = h;
+                tips[slot].he = 3 * (base + (k / 3) * B + tid) + k % 3;
                 atomicAdd(&d.ctr->ntips, 1);
             } else {
                 err = true;
             }
         }
-        if (err) atomicOr(&d.ctr->err, kErrCorrupt);
     }
+    if (err) atomicOr(&d.ctr->err, kErrCorrupt);
 }
 
 // ---------------------------------------------------------------------------
 // k_repair: middle edge of each barrier tip
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t set_repair_bit(uint8_t *tflag, int h) {
+// Sets the frontier bit of half-edge h; returns whether it was set before.
+__device__ __forceinline__ uint32_t set_frontier_bit(uint8_t *tflag, int h) {
     int t = h / 3, i = h - 3 * t;
     uint32_t *word = reinterpret_cast<uint32_t *>(tflag) + (t >> 2);
     uint32_t bit = (1u << (2 + i)) << (8 * (t & 3));
@@ -303,7 +533,8 @@ __device__ __forceinline__ uint32_t set_repair_bit(uint8_t *tflag, int h) {
 }
 
 __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *tips,
-                         int cap_tips, ListEntry *cands, int cap_cands, ListEntry *fixes, int cap_fix) {
+                         int cap_tips, ListEntry *walk, int32_t *walk_counts, int walk_cap, ListEntry *fixes,
+                         int cap_fix) {
     const int ntips = min(rc->ntips, cap_tips);
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ntips; k += gridDim.x * blockDim.x) {
         const ListEntry e = tips[k];
@@ -329,24 +560,26 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
         int m = a;
         for (int s = 0; s < deg / 2; s++) m = he_next(twin[m]);
         const int mt = twin[m];
-        uint32_t had_lo = set_repair_bit(d.tflag, m < mt ? m : mt);
-        set_repair_bit(d.tflag, m < mt ? mt : m);
+        uint32_t had_lo = set_frontier_bit(d.tflag, m < mt ? m : mt);
+        set_frontier_bit(d.tflag, m < mt ? mt : m);
         if (!had_lo) atomicAdd(&d.ctr->nmiddle, 1);
-        int c = atomicAdd(&rc->ncand, 2);
-        if (c + 1 < cap_cands) {
-            cands[c].mesh = e.mesh;
-            cands[c].he = m;
-            cands[c + 1].mesh = e.mesh;
-            cands[c + 1].he = mt;
+        // both halves of the middle edge seed the polygons on either side
+        const int stripe = k % kStripes;
+        const int c = atomicAdd(&walk_counts[stripe * kStripePad], 2);
+        if (c + 1 < walk_cap) {
+            walk[stripe * walk_cap + c].mesh = e.mesh;
+            walk[stripe * walk_cap + c].he = m;
+            walk[stripe * walk_cap + c + 1].mesh = e.mesh;
+            walk[stripe * walk_cap + c + 1].he = mt;
         } else {
             atomicOr(&d.ctr->err, kErrCorrupt);
         }
         int f = atomicAdd(&rc->nfix, 2);
         if (f + 1 < cap_fix) {
             fixes[f].mesh = e.mesh;
-            fixes[f].he = a;      // leaves the tip
+            fixes[f].he = a;        // leaves the tip
             fixes[f + 1].mesh = e.mesh;
-            fixes[f + 1].he = mt; // leaves the other endpoint of the middle edge
+            fixes[f + 1].he = mt;   // leaves the other end of the middle edge
         } else {
             atomicOr(&d.ctr->err, kErrCorrupt);
         }
@@ -361,15 +594,15 @@ __device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
     // e leaves the vertex x; prev(e) enters x in the same triangle
     const int32_t *__restrict__ twin = d.twin;
     const uint8_t *__restrict__ tflag = d.tflag;
-    int p = he_prev(e);
+    const int p = he_prev(e);
     bool ok = true;
-    if (is_frontier(twin, tflag, p)) {
-        int n = turn_next(twin, tflag, p);
+    if (is_frontier(tflag, p)) {
+        const int n = turn_next(twin, tflag, p);
         ok &= n >= 0;
         d.next_o[p] = n;
     }
-    if (is_frontier(twin, tflag, e)) {
-        int q = turn_prev(twin, tflag, e);
+    if (is_frontier(tflag, e)) {
+        const int q = turn_prev(twin, tflag, e);
         ok &= q >= 0;
         d.prev_o[e] = q;
     }
@@ -388,7 +621,7 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
         int e = o, steps = 0;
         do {   // clockwise over the outgoing half-edges
             ok &= fix_around(d, e);
-            int g = twin[e];
+            const int g = twin[e];
             if (g < 0) {
                 open = true;
                 break;
@@ -403,7 +636,7 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
             e = o;
             steps = 0;
             while (true) {
-                int g = twin[he_prev(e)];
+                const int g = twin[he_prev(e)];
                 if (g < 0) break;
                 e = g;
                 ok &= fix_around(d, e);
@@ -421,79 +654,143 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
 // k_walk: seed -> frontier half-edge -> loop minimum and length
 // ---------------------------------------------------------------------------
 
-// Walks the loop through frontier half-edge f; records (length, local index
-// of the minimum) in the minimum's triangle.  All seeds of one loop write the
-// same byte.
-__device__ __forceinline__ bool walk_record(const MeshDesc &d, int f) {
-    const int32_t *__restrict__ nx = d.next_o;
-    const int nh = 3 * d.nt;
-    int cur = f, mn = f, len = 0;
-    do {
-        mn = cur < mn ? cur : mn;
-        ++len;
-        cur = nx[cur];
-        if (cur < 0 || len > nh) return false;
-    } while (cur != f);
-    int t = mn / 3;
-    int code = ((len < kPlMax ? len : kPlMax) << 2) | (mn - 3 * t);
-    d.pl[t] = (uint8_t)code;
-    return true;
-}
-
 // From seed s, turn clockwise around origin(s) until a frontier half-edge.
-// After the fix-up, next_o[h] >= 0 exactly on frontier half-edges.
 __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
-    const int32_t *__restrict__ nx = d.next_o;
     int f = s;
     for (int k = 0; k < kRotGuard; k++) {
-        if (nx[f] >= 0) return f;
-        int g = d.twin[f];
+        if (is_frontier(d.tflag, f)) return f;
+        const int g = d.twin[f];
         if (g < 0) return -1;
         f = he_next(g);
     }
     return -1;
 }
 
+
+// Every entry of the walk list: from the seed to a frontier half-edge of its
+// polygon (a frontier half-edge of the seed's own triangle if it has one),
+// around the loop, and the loop recorded.  Each thread keeps ITEMS loops in
+// flight and advances them in lock-step; each loop's next' array and bound
+// sit in registers.
 template <int ITEMS>
-__global__ void k_walk(const MeshDesc *__restrict__ descs, int nmesh) {
-    const int tile = blockIdx.x;
-    const int mi = find_mesh<0>(descs, nmesh, tile);
-    const MeshDesc &d = descs[mi];
-    const int nt = d.nt;
-    const int base = (tile - d.tri_tile0) * (int)blockDim.x * ITEMS;
+__global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
+                                              const int32_t *walk_counts, int walk_cap) {
+    __shared__ int s_pref[kStripes + 1];
+    const int total = striped_prefix(walk_counts, walk_cap, s_pref);
+    const int nthreads = gridDim.x * blockDim.x;
+    for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
+        const int32_t *nx[ITEMS];
+        int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], len[ITEMS], lim[ITEMS];
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        int t = base + j * (int)blockDim.x + (int)threadIdx.x;
-        if (t >= nt) break;
-        uint32_t f = d.tflag[t];
-        if (!(f & kSeedBit)) continue;
-        int L = (int)(f & 3u);
-        // the seed triangle lies in the polygon; any of its frontier
-        // half-edges is on the polygon's loop
-        int s = -1;
-        for (int i = 1; i <= 3 && s < 0; i++) {
-            int h = 3 * t + (L + i) % 3;
-            if (d.next_o[h] >= 0) s = h;
+        for (int j = 0; j < ITEMS; j++) {
+            start[j] = cur[j] = mn[j] = -1;
+            len[j] = lim[j] = 0;
+            mesh[j] = 0;
+            nx[j] = nullptr;
+            const int g = g0 + j * nthreads;
+            if (g >= total) continue;
+            const ListEntry e = walk[striped_index(s_pref, walk_cap, g)];
+            const MeshDesc &d = descs[e.mesh];
+            mesh[j] = e.mesh;
+            nx[j] = d.next_o;
+            lim[j] = 3 * d.nt;
+            const int t = e.he / 3;
+            const uint32_t f = d.tflag[t];
+            int st = fbit(f, e.he - 3 * t) ? e.he : -1;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                if (st < 0 && fbit(f, i)) st = 3 * t + i;
+            if (st < 0) st = seek_frontier(d, e.he);
+            if (st < 0) {
+                atomicOr(&d.ctr->err, kErrCorrupt);
+                continue;
+            }
+            start[j] = cur[j] = mn[j] = st;
         }
-        if (s < 0) s = seek_frontier(d, 3 * t + L);
-        if (s < 0 || !walk_record(d, s)) atomicOr(&d.ctr->err, kErrCorrupt);
+        bool active = true;
+        while (active) {
+            active = false;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if (start[j] < 0) continue;
+                mn[j] = cur[j] < mn[j] ? cur[j] : mn[j];
+                ++len[j];
+                cur[j] = nx[j][cur[j]];
+                if (cur[j] < 0 || len[j] > lim[j]) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    start[j] = -1;
+                    continue;
+                }
+                if (cur[j] == start[j]) {
+                    record_loop(descs[mesh[j]], mn[j], len[j]);
+                    start[j] = -1;
+                    continue;
+                }
+                active = true;
+            }
+        }
     }
 }
 
-__global__ void k_walk_rep(const MeshDesc *__restrict__ descs, RunCounters *rc,
-                           const ListEntry *cands, int cap_cands) {
-    const int n = min(rc->ncand, cap_cands);
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const ListEntry e = cands[k];
-        const MeshDesc &d = descs[e.mesh];
-        int s = seek_frontier(d, e.he);
-        if (s < 0 || !walk_record(d, s)) atomicOr(&d.ctr->err, kErrCorrupt);
+// The loops k_compact left out: each written from its minimum at its offset.
+template <int ITEMS>
+__global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs, const EmitEntry *emit,
+                                              const int32_t *emit_counts, int emit_cap) {
+    __shared__ int s_pref[kStripes + 1];
+    const int total = striped_prefix(emit_counts, emit_cap, s_pref);
+    const int nthreads = gridDim.x * blockDim.x;
+    for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
+        const int32_t *nx[ITEMS];
+        int32_t *out[ITEMS];
+        int mesh[ITEMS], cur[ITEMS], mn[ITEMS], pos[ITEMS], lim[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            cur[j] = -1;
+            mesh[j] = mn[j] = pos[j] = lim[j] = 0;
+            nx[j] = nullptr;
+            out[j] = nullptr;
+            const int g = g0 + j * nthreads;
+            if (g >= total) continue;
+            const EmitEntry e = emit[striped_index(s_pref, emit_cap, g)];
+            const MeshDesc &d = descs[e.mesh];
+            mesh[j] = e.mesh;
+            nx[j] = d.next_o;
+            out[j] = d.loop_he;
+            cur[j] = mn[j] = e.mn;
+            pos[j] = e.off;
+            lim[j] = 3 * d.nt;
+        }
+        bool active = true;
+        while (active) {
+            active = false;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if (cur[j] < 0) continue;
+                if (pos[j] >= lim[j]) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    cur[j] = -1;
+                    continue;
+                }
+                out[j][pos[j]++] = cur[j];
+                cur[j] = nx[j][cur[j]];
+                if (cur[j] < 0) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    continue;
+                }
+                if (cur[j] == mn[j]) {
+                    cur[j] = -1;
+                    continue;
+                }
+                active = true;
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_compact: decoupled look-back scan of (loop count, loop length) per mesh,
-// then each loop is written starting at its minimum
+// k_compact: decoupled look-back scan of (loop count, loop length) per mesh;
+// each tile assembles its seeds, offsets and loops in LDS and writes them out
+// contiguously
 // ---------------------------------------------------------------------------
 
 constexpr uint64_t kFlagAgg = 1ull << 62;
@@ -501,11 +798,10 @@ constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr int kSpinGuard = 1 << 26;
 
 __device__ __forceinline__ uint64_t pack_status(uint64_t flag, int cnt, int sum) {
-    return flag | ((uint64_t)(uint32_t)cnt << 32 & 0x3fffffff00000000ull) | (uint32_t)sum;
+    return flag | (((uint64_t)(uint32_t)cnt << 32) & 0x3fffffff00000000ull) | (uint32_t)sum;
 }
 
-// Length of the loop starting at its minimum mn (used when it did not fit in
-// the per-triangle byte).
+// Length of the loop starting at mn (when it did not fit in the byte).
 __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
     const int nh = 3 * d.nt;
     int cur = mn, len = 0;
@@ -517,37 +813,93 @@ __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
     return len;
 }
 
+// Decoupled look-back by one wave: lane k inspects tile (end - k); tiles
+// before the mesh's first tile count as an inclusive zero.  Returns the
+// exclusive prefix (count, sum) of `tile` within its mesh.
+__device__ __forceinline__ void wave_lookback(uint64_t *status, int tile, int first, int &pc, int &ps,
+                                              bool &bad) {
+    const int lane = __lane_id();
+    pc = 0;
+    ps = 0;
+    int end = tile - 1, spins = 0;
+    while (true) {
+        const int idx = end - lane;
+        uint64_t st = idx < first ? kFlagInc
+                                  : __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (__ballot((st >> 62) == 0ull) != 0ull) {
+            if (++spins > kSpinGuard) {
+                bad = true;
+                st = kFlagInc;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((st >> 62) == 0ull)
+                st = __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned long long inc = __ballot((st >> 62) == 2ull);
+        const int stop = inc ? __ffsll((long long)inc) - 1 : kWave - 1;
+        const int c = lane <= stop ? (int)((st >> 32) & 0x3fffffffull) : 0;
+        const int v = lane <= stop ? (int)(uint32_t)st : 0;
+        pc += wave_sum(c);
+        ps += wave_sum(v);
+        if (inc) break;
+        end -= kWave;
+    }
+}
+
 template <int ITEMS>
-__global__ void k_compact(const MeshDesc *__restrict__ descs, int nmesh, RunCounters *rc,
-                          uint64_t *status) {
+__global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
+                                                  RunCounters *rc, uint64_t *status, EmitEntry *emit,
+                                                  int32_t *emit_counts, int emit_cap) {
+    // LDS: loop half-edges (3 per triangle of the tile), seeds and local
+    // offsets (one per triangle)
+    extern __shared__ int4 lds_raw[];
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int TB = B * ITEMS;
+    int *s_he = reinterpret_cast<int *>(lds_raw);
+    int *s_seed = s_he + 3 * TB;
+    int *s_off = s_seed + TB;
     __shared__ int s_tile;
-    __shared__ int lds[80];
+    __shared__ int s_scan[72];
     __shared__ int s_prefix[2];
-    if (threadIdx.x == 0) s_tile = atomicAdd(&rc->tile_ctr, 1);
+    if (tid == 0) s_tile = atomicAdd(&rc->tile_ctr, 1);
     __syncthreads();
     const int tile = s_tile;
     const int mi = find_mesh<2>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
-    const int nt = d.nt;
+    const int nt = d.nt, nh = 3 * nt;
     const int ltile = tile - d.cmp_tile0;
-    const int per_tile = (int)blockDim.x * ITEMS;
-    const int mesh_tiles = nt > 0 ? (nt + per_tile - 1) / per_tile : 1;
-    const int t0 = ltile * per_tile + (int)threadIdx.x * ITEMS;
+    const int mesh_tiles = nt > 0 ? (nt + TB - 1) / TB : 1;
+    const int t0 = ltile * TB + tid * ITEMS;
+    const int32_t *__restrict__ nx = d.next_o;
 
-    // 1. this thread's loop minima and lengths (contiguous triangles)
-    uint8_t code[ITEMS];
+    // 1. loop minima and lengths of this thread's ITEMS contiguous triangles
+    uint8_t code[ITEMS], fl[ITEMS];
+    if (ITEMS == 4 && t0 + 4 <= nt) {
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(d.pl + t0);
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(d.tflag + t0);
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            code[j] = (uint8_t)(w >> (8 * (j & 3)));
+            fl[j] = (uint8_t)(v >> (8 * (j & 3)));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            code[j] = t0 + j < nt ? d.pl[t0 + j] : 0;
+            fl[j] = t0 + j < nt ? d.tflag[t0 + j] : 0;
+        }
+    }
     int lens[ITEMS];
     int cnt = 0, sum = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        int t = t0 + j;
-        code[j] = t < nt ? d.pl[t] : 0;
         lens[j] = 0;
         if (code[j]) {
             int len = code[j] >> 2;
-            if (len >= kPlMax) len = loop_length(d, 3 * t + (code[j] & 3));
-            if (len < 0) {
+            if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
+            if (len <= 0) {
                 bad = true;
                 len = 0;
             }
@@ -556,70 +908,136 @@ __global__ void k_compact(const MeshDesc *__restrict__ descs, int nmesh, RunCoun
             sum += len;
         }
     }
-    // 2. block scan
+    // 2. block scan (tile-local offsets)
     int ecnt, esum, tcnt, tsum;
-    block_excl_scan2(cnt, sum, ecnt, esum, tcnt, tsum, lds);
-    // 3. look-back over the tiles of the same mesh
-    if (threadIdx.x == 0) {
+    block_excl_scan2(cnt, sum, ecnt, esum, tcnt, tsum, s_scan);
+    // 3. look-back over the tiles of the same mesh (first wave)
+    if (tid < kWave) {
         int pc = 0, ps = 0;
         if (ltile == 0) {
-            __hip_atomic_store(&status[tile], pack_status(kFlagInc, tcnt, tsum), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0)
+                __hip_atomic_store(&status[tile], pack_status(kFlagInc, tcnt, tsum), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&status[tile], pack_status(kFlagAgg, tcnt, tsum), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int k = tile - 1;
-            int spins = 0;
-            while (true) {
-                uint64_t st = __hip_atomic_load(&status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                uint64_t flag = st & (3ull << 62);
-                if (flag == 0ull) {
-                    if (++spins > kSpinGuard) {
-                        atomicOr(&d.ctr->err, kErrCorrupt);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                pc += (int)((st >> 32) & 0x3fffffffull);
-                ps += (int)(uint32_t)st;
-                if (flag == kFlagInc || k == d.cmp_tile0) break;
-                --k;
-            }
-            __hip_atomic_store(&status[tile], pack_status(kFlagInc, pc + tcnt, ps + tsum),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0)
+                __hip_atomic_store(&status[tile], pack_status(kFlagAgg, tcnt, tsum), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            wave_lookback(status, tile, d.cmp_tile0, pc, ps, bad);
+            if (tid == 0)
+                __hip_atomic_store(&status[tile], pack_status(kFlagInc, pc + tcnt, ps + tsum), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_prefix[0] = pc;
-        s_prefix[1] = ps;
-        if (ltile == mesh_tiles - 1) {
-            d.ctr->npoly = pc + tcnt;
-            d.ctr->nloop = ps + tsum;
-            d.loop_off[pc + tcnt] = ps + tsum;
+        if (tid == 0) {
+            s_prefix[0] = pc;
+            s_prefix[1] = ps;
+            if (ltile == mesh_tiles - 1) {
+                d.ctr->npoly = pc + tcnt;
+                d.ctr->nloop = ps + tsum;
+                d.loop_off[pc + tcnt] = ps + tsum;
+            }
         }
     }
     __syncthreads();
-    // 4. emit seeds, offsets and loops
-    const int nh = 3 * nt;
-    int p = s_prefix[0] + ecnt, off = s_prefix[1] + esum;
+    const int pc = s_prefix[0], ps = s_prefix[1];
+    const bool fits = tsum <= 3 * TB && pc + tcnt <= nt && ps + tsum <= nh;
+    // 4. seeds, local offsets and loops; into LDS, or straight to global
+    //    memory for a tile whose loops do not fit
+    int *he_out = fits ? s_he : d.loop_he + ps;
+    // A loop of 3 is one triangle: (mn, next, prev).  A loop of 4 is two
+    // triangles: the minimum's triangle has frontier half-edges a, b = next(a)
+    // and crosses to the other triangle at b, whose two frontier half-edges
+    // follow as p1 = next'(b), next(p1).  Longer loops get their offset here
+    // and are written by k_emit.
+    int q = ecnt, off = esum;
+    int pos[ITEMS], p1[ITEMS];
+    bool quad[ITEMS], defer[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
+        pos[j] = 0;
+        p1[j] = -1;
+        quad[j] = defer[j] = false;
         if (!code[j]) continue;
-        int t = t0 + j;
-        int mn = 3 * t + (code[j] & 3);
-        if (p >= nt || off + lens[j] > nh) {  // only reachable with corrupt lengths
+        const int t = t0 + j, mn = 3 * t + (code[j] & 3);
+        const bool place = fits || (pc + q < nt && ps + off + lens[j] <= nh);
+        if (!place) {
             bad = true;
-            break;
+        } else {
+            if (fits) {
+                s_seed[q] = mn;
+                s_off[q] = off;
+            } else {
+                d.seeds[pc + q] = mn;
+                d.loop_off[pc + q] = ps + off;
+            }
+            const uint32_t fb = (fl[j] >> 2) & 7u;
+            if (lens[j] == 3) {
+                he_out[off] = mn;
+                he_out[off + 1] = he_next(mn);
+                he_out[off + 2] = he_prev(mn);
+            } else if (lens[j] == 4 && __popc(fb) == 2) {
+                const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);   // non-frontier edge
+                const int bb = 3 * t + (sx == 0 ? 2 : sx - 1);
+                p1[j] = nx[bb];
+                pos[j] = off;
+                quad[j] = true;
+            } else if (lens[j] > 0) {
+                pos[j] = ps + off;
+                defer[j] = true;
+            }
         }
-        d.seeds[p] = mn;
-        d.loop_off[p] = off;
-        int cur = mn;
-        for (int k = 0; k < lens[j] && cur >= 0; k++) {
-            d.loop_he[off + k] = cur;
-            cur = d.next_o[cur];
-        }
-        if (cur != mn) bad = true;
-        ++p;
+        ++q;
         off += lens[j];
+    }
+    {   // longer loops go to the emit list (stripe by tile, one atomic per block)
+        __shared__ int s_base;
+        int nd = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) nd += defer[j];
+        bool full = false;
+        int e = block_reserve(emit_counts, emit_cap, tile % kStripes, nd, s_scan, &s_base, &full);
+        const int lim = (tile % kStripes + 1) * emit_cap;
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            if (!defer[j]) continue;
+            if (e < lim) {
+                emit[e].mesh = mi;
+                emit[e].mn = 3 * (t0 + j) + (code[j] & 3);
+                emit[e].off = pos[j];
+            }
+            ++e;
+        }
+        bad |= full;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        if (!quad[j]) continue;
+        const uint32_t fb = (fl[j] >> 2) & 7u;
+        const int t = t0 + j, mn = 3 * t + (code[j] & 3);
+        const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
+        const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
+        const int o = pos[j];
+        if (p1[j] < 0 || (mn != aa && mn != bb)) {
+            bad = true;
+        } else if (mn == aa) {
+            he_out[o] = aa;
+            he_out[o + 1] = bb;
+            he_out[o + 2] = p1[j];
+            he_out[o + 3] = he_next(p1[j]);
+        } else {
+            he_out[o] = bb;
+            he_out[o + 1] = p1[j];
+            he_out[o + 2] = he_next(p1[j]);
+            he_out[o + 3] = aa;
+        }
+    }
+    if (fits) {
+        __syncthreads();
+        // contiguous stores of the tile's part of seeds, loop_off, loop_he
+        for (int k = tid; k < tcnt; k += B) {
+            d.seeds[pc + k] = s_seed[k];
+            d.loop_off[pc + k] = ps + s_off[k];
+        }
+        for (int k = tid; k < tsum; k += B) d.loop_he[ps + k] = s_he[k];
     }
     if (bad) atomicOr(&d.ctr->err, kErrCorrupt);
 }
@@ -628,19 +1046,19 @@ __global__ void k_compact(const MeshDesc *__restrict__ descs, int nmesh, RunCoun
 // host launch of the whole chain
 // ---------------------------------------------------------------------------
 
-#define GP_LAUNCH_ITEMS(KER, ITEMS_RT, GRID, BLOCK, STREAM, ...)                                 \
+#define GP_LAUNCH_ITEMS(KER, ITEMS_RT, GRID, BLOCK, LDS, STREAM, ...)                            \
     do {                                                                                      \
         switch (ITEMS_RT) {                                                                   \
-            case 1: hipLaunchKernelGGL(KER<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;  \
-            case 2: hipLaunchKernelGGL(KER<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;  \
-            case 4: hipLaunchKernelGGL(KER<4>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;  \
-            case 8: hipLaunchKernelGGL(KER<8>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;  \
+            case 1: hipLaunchKernelGGL(KER<1>, GRID, BLOCK, LDS, STREAM, __VA_ARGS__); break; \
+            case 2: hipLaunchKernelGGL(KER<2>, GRID, BLOCK, LDS, STREAM, __VA_ARGS__); break; \
+            case 4: hipLaunchKernelGGL(KER<4>, GRID, BLOCK, LDS, STREAM, __VA_ARGS__); break; \
+            case 8: hipLaunchKernelGGL(KER<8>, GRID, BLOCK, LDS, STREAM, __VA_ARGS__); break; \
             default: return hipErrorInvalidValue;                                             \
         }                                                                                     \
     } while (0)
 
-hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s,
-                           launch_hook hook, void *user) {
+hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, launch_hook hook,
+                           void *user) {
     auto H = [&](int k, int after) {
         if (hook) hook(user, k, after);
     };
@@ -653,25 +1071,29 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
         int grid = (n + 255) / 256;
         grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
         hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, rb.rc, rb.ctrs, rb.nmesh, rb.status,
-                           rb.cmp_tiles);
+                           rb.cmp_tiles, rb.walk_counts, rb.emit_counts);
     }
     H(K_INIT, 1);
 
     H(K_LABEL, 0);
-    if (rb.tri_tiles > 0)
-        GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label), s,
-                        rb.descs, rb.nmesh);
+    GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label),
+                    sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh);
     H(K_LABEL, 1);
 
+    H(K_FRONTIER, 0);
+    GP_LAUNCH_ITEMS(k_frontier, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
+                    sizeof(int) * 3 * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh);
+    H(K_FRONTIER, 1);
+
     H(K_RELINK, 0);
-    if (rb.he_tiles > 0)
-        GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink), s,
-                        rb.descs, rb.nmesh, rb.rc, rb.tips, rb.cap_tips);
+    GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
+                    sizeof(int) * 6 * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
+                    rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap);
     H(K_RELINK, 1);
 
     H(K_REPAIR, 0);
-    hipLaunchKernelGGL(k_repair, dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.tips, rb.cap_tips,
-                       rb.cands, rb.cap_cands, rb.fixes, rb.cap_fix);
+    hipLaunchKernelGGL(k_repair, dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.tips, rb.cap_tips, rb.walk,
+                       rb.walk_counts, rb.walk_cap, rb.fixes, rb.cap_fix);
     H(K_REPAIR, 1);
 
     H(K_FIXUP, 0);
@@ -679,17 +1101,18 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
-    if (rb.tri_tiles > 0)
-        GP_LAUNCH_ITEMS(k_walk, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label), s,
-                        rb.descs, rb.nmesh);
-    hipLaunchKernelGGL(k_walk_rep, dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.cands, rb.cap_cands);
+    hipLaunchKernelGGL(k_walk<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.walk, rb.walk_counts, rb.walk_cap);
     H(K_WALK, 1);
 
     H(K_COMPACT, 0);
-    if (rb.cmp_tiles > 0)
-        GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact), s,
-                        rb.descs, rb.nmesh, rb.rc, rb.status);
+    GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
+                    sizeof(int) * 5 * (size_t)cfg.block_compact * cfg.items_compact, s, rb.descs, rb.nmesh,
+                    rb.rc, rb.status, rb.emit, rb.emit_counts, rb.emit_cap);
     H(K_COMPACT, 1);
+
+    H(K_EMIT, 0);
+    hipLaunchKernelGGL(k_emit<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.emit, rb.emit_counts, rb.emit_cap);
+    H(K_EMIT, 1);
     return hipGetLastError();
 }
 

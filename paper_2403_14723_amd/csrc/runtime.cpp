@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -12,165 +14,9 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/gpolylla.h"
-#include "gp_internal.h"
+#include "runtime_internal.h"
 
-namespace {
-
-constexpr size_t kAlign = 256;
-
-inline size_t align_up(size_t n, size_t a = kAlign) { return (n + a - 1) / a * a; }
-
-// ---------------------------------------------------------------------------
-// caching device allocator: blocks are kept after release and handed out
-// again for requests of up to 12.5% smaller size.  All users of one pool run
-// on one stream, so reuse after release is ordered by the stream.
-// ---------------------------------------------------------------------------
-class DevPool {
-  public:
-    size_t cap = 0;
-    size_t held = 0;
-    size_t in_use = 0;
-
-    int alloc(size_t n, void **p) {
-        n = align_up(n ? n : kAlign);
-        auto it = free_.lower_bound(n);
-        if (it != free_.end() && it->first <= n + n / 8) {
-            *p = it->second;
-            in_use += it->first;
-            used_[*p] = it->first;
-            free_.erase(it);
-            return GP_OK;
-        }
-        if (cap && held + n > cap) trim();
-        if (cap && held + n > cap) return GP_ENOMEM;
-        void *q = nullptr;
-        if (hipMalloc(&q, n) != hipSuccess) {
-            (void)hipGetLastError();
-            trim();
-            if (hipMalloc(&q, n) != hipSuccess) {
-                (void)hipGetLastError();
-                return GP_ENOMEM;
-            }
-        }
-        held += n;
-        in_use += n;
-        used_[q] = n;
-        *p = q;
-        return GP_OK;
-    }
-    void release(void *p) {
-        if (!p) return;
-        auto it = used_.find(p);
-        if (it == used_.end()) return;
-        in_use -= it->second;
-        free_.emplace(it->second, p);
-        used_.erase(it);
-    }
-    void trim() {
-        for (auto &kv : free_) {
-            (void)hipFree(kv.second);
-            held -= kv.first;
-        }
-        free_.clear();
-    }
-    void destroy() {
-        trim();
-        for (auto &kv : used_) (void)hipFree(kv.first);
-        used_.clear();
-        held = in_use = 0;
-    }
-
-  private:
-    std::multimap<size_t, void *> free_;
-    std::unordered_map<void *, size_t> used_;
-};
-
-// A bump arena carved out of one pool block.
-struct Arena {
-    char *base = nullptr;
-    size_t size = 0, off = 0;
-    template <class T>
-    T *take(size_t count) {
-        size_t n = align_up(count * sizeof(T));
-        T *p = reinterpret_cast<T *>(base + off);
-        off += n;
-        return p;
-    }
-};
-
-template <class T>
-size_t arena_bytes(size_t count) {
-    return align_up(count * sizeof(T));
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// objects
-// ---------------------------------------------------------------------------
-
-struct RunState;
-
-struct gp_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    DevPool pool;
-    gp::LaunchCfg cfg;
-    bool profile = false;
-    struct Pending {
-        int kernel;
-        hipEvent_t a, b;
-    };
-    std::vector<Pending> pending;
-    std::vector<hipEvent_t> spare_events;
-    hipEvent_t open_ev[gp::K_COUNT] = {};
-    double kms[gp::K_COUNT] = {};
-    int64_t kcount[gp::K_COUNT] = {};
-    // pinned host memory: cached blocks, descriptor staging ring, and runs
-    // whose results were freed before their work finished
-    std::multimap<size_t, void *> pinned_free;
-    struct Slot {
-        void *ptr = nullptr;
-        size_t bytes = 0;
-        hipEvent_t ev = nullptr;
-        bool armed = false;
-    };
-    Slot ring[4];
-    int ring_next = 0;
-    std::vector<RunState *> retired;
-};
-
-struct gp_mesh {
-    gp_ctx *ctx = nullptr;
-    int32_t nv = 0, nt = 0;
-    int64_t nflipped = 0;
-    int2 *xy = nullptr;
-    int32_t *org = nullptr;
-    int32_t *twin = nullptr;
-};
-
-struct RunState {
-    gp_ctx *ctx = nullptr;
-    void *out_block = nullptr;        // outputs of every mesh of the run
-    gp::MeshCounters *host_ctrs = nullptr;  // pinned
-    size_t host_ctrs_bytes = 0;
-    int nmesh = 0;
-    hipEvent_t done = nullptr;
-    bool synced = false;
-    int status = GP_OK;
-    int refs = 0;
-};
-
-struct gp_result {
-    RunState *run = nullptr;
-    int index = 0;
-    int32_t nt = 0, nv = 0;
-    int64_t nflipped = 0;
-    int32_t *next_o = nullptr, *prev_o = nullptr, *seeds = nullptr, *loop_off = nullptr,
-            *loop_he = nullptr;
-};
+using namespace gprt;
 
 namespace {
 
@@ -181,17 +27,6 @@ namespace {
             return GP_EHIP;                                 \
         }                                                   \
     } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 hipEvent_t take_event(gp_ctx *c) {
     if (!c->spare_events.empty()) {
@@ -352,6 +187,213 @@ void run_unref(RunState *r) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// run planning: tile spaces, list capacities, scratch layout
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Plan {
+    std::vector<gp::MeshDesc> descs;   // sizes and tile offsets filled in
+    std::vector<int32_t> nts;
+    int64_t tri_tiles = 0, he_tiles = 0, cmp_tiles = 0, cap_tips = 0, cap_fix = 0;
+    int64_t walk_cap = 0, emit_cap = 0;
+    size_t out_bytes = 0, tmp_bytes = 0, tmp_mesh = 0;
+};
+
+int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Plan *p) {
+    const int64_t tt = (int64_t)cfg.block_label * cfg.items_label;
+    const int64_t th = (int64_t)cfg.block_relink * cfg.items_relink;
+    const int64_t tc = (int64_t)cfg.block_compact * cfg.items_compact;
+    p->descs.assign(n, gp::MeshDesc{});
+    p->nts.resize(n);
+    for (int i = 0; i < n; i++) {
+        const gp_mesh *m = meshes[i];
+        gp::MeshDesc &d = p->descs[i];
+        d.nt = m->nt;
+        d.nv = m->nv;
+        d.tri_tile0 = (int32_t)p->tri_tiles;
+        d.he_tile0 = (int32_t)p->he_tiles;
+        d.cmp_tile0 = (int32_t)p->cmp_tiles;
+        p->nts[i] = m->nt;
+        p->tri_tiles += gp::tiles_for(m->nt, tt);
+        p->he_tiles += gp::tiles_for(m->nt, th);
+        p->cmp_tiles += gp::tiles_for(m->nt, tc);
+        p->cap_tips += m->nt / 2 + 2;   // tips are interior vertices: at most T/2 + 1
+        const int64_t nh = 3ll * m->nt;
+        p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(m->nt + 1) +
+                        arena_bytes<int32_t>(m->nt + 2);
+        p->tmp_mesh += arena_bytes<uint8_t>(align_up(m->nt + 4, 4)) + arena_bytes<uint8_t>(m->nt + 1);
+    }
+    if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
+    p->cap_fix = 2 * p->cap_tips;
+    // striped lists, sized for the worst case: every triangle of a tile holds
+    // a seed (walk) or a loop minimum (emit); repair seeds spread evenly
+    const int64_t S = gp::kStripes;
+    p->walk_cap = (p->he_tiles + S - 1) / S * th + (2 * p->cap_tips + S - 1) / S + 2;
+    p->emit_cap = (p->cmp_tiles + S - 1) / S * tc;
+    if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff) return GP_ERANGE;
+    p->tmp_bytes = p->tmp_mesh + arena_bytes<gp::MeshDesc>(n) + arena_bytes<gp::RunCounters>(1) +
+                   arena_bytes<gp::MeshCounters>(n) + arena_bytes<gp::ListEntry>(p->cap_tips) +
+                   arena_bytes<gp::ListEntry>(p->cap_fix) + arena_bytes<uint64_t>(p->cmp_tiles) +
+                   arena_bytes<gp::ListEntry>(p->walk_cap * S) + arena_bytes<gp::EmitEntry>(p->emit_cap * S) +
+                   2 * arena_bytes<int32_t>(S * gp::kStripePad);
+    return GP_OK;
+}
+
+void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp::RunBuffers *rb,
+                    uint8_t **tflag, uint8_t **pl) {
+    const int n = (int)p.descs.size();
+    const int64_t S = gp::kStripes;
+    Arena at{static_cast<char *>(block), p.tmp_bytes, 0};
+    *rb = gp::RunBuffers{};
+    rb->descs = at.take<gp::MeshDesc>(n);
+    rb->nmesh = n;
+    rb->tri_tiles = (int32_t)p.tri_tiles;
+    rb->he_tiles = (int32_t)p.he_tiles;
+    rb->cmp_tiles = (int32_t)p.cmp_tiles;
+    rb->rc = at.take<gp::RunCounters>(1);
+    rb->ctrs = at.take<gp::MeshCounters>(n);
+    rb->tips = at.take<gp::ListEntry>(p.cap_tips);
+    rb->fixes = at.take<gp::ListEntry>(p.cap_fix);
+    rb->cap_tips = (int32_t)p.cap_tips;
+    rb->cap_fix = (int32_t)p.cap_fix;
+    rb->status = at.take<uint64_t>(p.cmp_tiles);
+    rb->walk = at.take<gp::ListEntry>(p.walk_cap * S);
+    rb->walk_counts = at.take<int32_t>(S * gp::kStripePad);
+    rb->walk_cap = (int32_t)p.walk_cap;
+    rb->emit = at.take<gp::EmitEntry>(p.emit_cap * S);
+    rb->emit_counts = at.take<int32_t>(S * gp::kStripePad);
+    rb->emit_cap = (int32_t)p.emit_cap;
+    for (int i = 0; i < n; i++) {
+        tflag[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));
+        pl[i] = at.take<uint8_t>(meshes[i]->nt + 1);
+    }
+}
+
+}  // namespace
+
+namespace gprt {
+
+size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device) {
+    const int64_t nh = 3 * nt;
+    const size_t keep = align_up(sizeof(int2) * (size_t)std::max<int64_t>(nv, 1)) +
+                        2 * align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1));
+    const size_t tmp = arena_bytes<int32_t>(nv + 1) * 3 + arena_bytes<int32_t>(nh + 1) +
+                       arena_bytes<uint64_t>(gp::build_scan_tiles((int32_t)nv)) + arena_bytes<int32_t>(4) +
+                       arena_bytes<unsigned long long>(1) + (inputs_on_device ? 0 : arena_bytes<int32_t>(nh + 1));
+    return keep + align_up(tmp);
+}
+
+size_t batch_footprint(const gp::LaunchCfg &cfg, const int32_t *nts, int n) {
+    std::vector<gp_mesh> shapes(n);
+    std::vector<const gp_mesh *> ptrs(n);
+    for (int i = 0; i < n; i++) {
+        shapes[i].nt = nts[i];
+        ptrs[i] = &shapes[i];
+    }
+    Plan p;
+    if (make_plan(cfg, ptrs.data(), n, &p) != GP_OK) return (size_t)-1;
+    return align_up(p.out_bytes) + align_up(p.tmp_bytes);
+}
+
+}  // namespace gprt
+
+namespace {
+
+// A captured pipeline for one batch shape.  Its scratch (descriptor table,
+// counters, lists, labels) stays allocated with it, so every kernel argument
+// in the graph stays valid; per call only the descriptor table is rewritten
+// (output pointers) before the replay.
+struct GraphEntry {
+    gp::LaunchCfg cfg;
+    std::vector<int32_t> nts;
+    void *scratch = nullptr;
+    gp::RunBuffers rb{};
+    std::vector<uint8_t *> tflag, pl;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+bool same_cfg(const gp::LaunchCfg &a, const gp::LaunchCfg &b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+}  // namespace
+
+namespace gprt {
+struct GraphCache {
+    std::vector<GraphEntry> entries;
+    uint64_t tick = 0;
+};
+}  // namespace gprt
+
+namespace {
+
+GraphCache &graphs_of(gp_ctx *c);
+
+void graph_entry_free(gp_ctx *c, GraphEntry &e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    c->pool.release(e.scratch);   // stream-ordered reuse
+    e.exec = nullptr;
+    e.scratch = nullptr;
+}
+
+int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
+    GraphCache &gc = graphs_of(c);
+    for (auto &e : gc.entries) {
+        if (e.nts == plan.nts && same_cfg(e.cfg, c->cfg)) {
+            e.last_use = ++gc.tick;
+            *out = &e;
+            return GP_OK;
+        }
+    }
+    if (gc.entries.size() >= 4) {   // evict the least recently used shape
+        size_t k = 0;
+        for (size_t i = 1; i < gc.entries.size(); i++)
+            if (gc.entries[i].last_use < gc.entries[k].last_use) k = i;
+        graph_entry_free(c, gc.entries[k]);
+        gc.entries.erase(gc.entries.begin() + k);
+    }
+    GraphEntry e;
+    e.cfg = c->cfg;
+    e.nts = plan.nts;
+    int rc = c->pool.alloc(plan.tmp_bytes, &e.scratch);
+    if (rc != GP_OK) return rc;
+    const int n = (int)plan.nts.size();
+    e.tflag.resize(n);
+    e.pl.resize(n);
+    // layout_scratch only needs the sizes of the meshes
+    std::vector<gp_mesh> shapes(n);
+    std::vector<const gp_mesh *> ptrs(n);
+    for (int i = 0; i < n; i++) {
+        shapes[i].nt = plan.nts[i];
+        ptrs[i] = &shapes[i];
+    }
+    layout_scratch(plan, e.scratch, ptrs.data(), &e.rb, e.tflag.data(), e.pl.data());
+    hipGraph_t graph = nullptr;
+    hipStream_t s = c->stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        c->pool.release(e.scratch);
+        return GP_EHIP;
+    }
+    hipError_t le = gp::launch_pipeline(c->cfg, e.rb, s, nullptr, nullptr);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph ||
+        hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        c->pool.release(e.scratch);
+        return GP_EHIP;
+    }
+    (void)hipGraphDestroy(graph);
+    e.last_use = ++gc.tick;
+    gc.entries.push_back(std::move(e));
+    *out = &gc.entries.back();
+    return GP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 
@@ -405,6 +447,48 @@ int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
             c->cfg.items_label = c->cfg.items_relink = c->cfg.items_compact = opts->items;
         }
     }
+    {
+        // optional per-kernel launch shapes, "label=256x4,relink=256x4,compact=256x4,persist=1024x256"
+        // (the autotuner's hook); malformed entries are ignored
+        gp::LaunchCfg &g = c->cfg;
+        if (const char *env = std::getenv("GPOLYLLA_CFG")) {
+            std::string spec(env);
+            size_t p0 = 0;
+            while (p0 < spec.size()) {
+                size_t p1 = spec.find(',', p0);
+                if (p1 == std::string::npos) p1 = spec.size();
+                std::string item = spec.substr(p0, p1 - p0);
+                p0 = p1 + 1;
+                size_t eq = item.find('='), x = item.find('x');
+                if (eq == std::string::npos || x == std::string::npos || x < eq) continue;
+                int b = std::atoi(item.substr(eq + 1, x - eq - 1).c_str());
+                int it = std::atoi(item.substr(x + 1).c_str());
+                std::string k = item.substr(0, eq);
+                bool ok_b = b >= 64 && b <= 1024 && b % 64 == 0;
+                bool ok_i = it == 1 || it == 2 || it == 4 || it == 8;
+                if (k == "persist") {
+                    if (b >= 64 && b <= 1024 && b % 64 == 0 && it >= 1 && it <= 65536) {
+                        g.block_persistent = b;
+                        g.persistent_blocks = it;
+                    }
+                    continue;
+                }
+                if (!ok_b || !ok_i) continue;
+                if (k == "label") { g.block_label = b; g.items_label = it; }
+                else if (k == "relink") { g.block_relink = b; g.items_relink = it; }
+                else if (k == "compact") { g.block_compact = b; g.items_compact = it; }
+            }
+        }
+    }
+    {
+        // LDS per tile: k_label and k_frontier stage 12 bytes per triangle
+        // (tile <= 4096), k_relink 24 bytes (tile <= 1024), k_compact 20
+        // bytes (tile <= 2048)
+        gp::LaunchCfg &g = c->cfg;
+        while ((int64_t)g.block_label * g.items_label > 4096 && g.items_label > 1) g.items_label /= 2;
+        while ((int64_t)g.block_relink * g.items_relink > 1024 && g.items_relink > 1) g.items_relink /= 2;
+        while ((int64_t)g.block_compact * g.items_compact > 2048 && g.items_compact > 1) g.items_compact /= 2;
+    }
     if (opts && opts->stream) {
         c->stream = static_cast<hipStream_t>(opts->stream);
     } else {
@@ -425,6 +509,11 @@ void gpolylla_ctx_destroy(gp_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     resolve_profile(c);
     reap_retired(c, true);
+    if (c->graphs) {
+        for (auto &e : c->graphs->entries) graph_entry_free(c, e);
+        delete c->graphs;
+        c->graphs = nullptr;
+    }
     for (auto e : c->spare_events) (void)hipEventDestroy(e);
     c->pool.destroy();
     for (auto &kv : c->pinned_free) (void)hipHostFree(kv.second);
@@ -610,45 +699,30 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     }
     if (n == 0) return GP_OK;
     DeviceGuard g(c->device);
-    const gp::LaunchCfg &cfg = c->cfg;
-    const int64_t tt = (int64_t)cfg.block_label * cfg.items_label;
-    const int64_t th = (int64_t)cfg.block_relink * cfg.items_relink;
-    const int64_t tc = (int64_t)cfg.block_compact * cfg.items_compact;
+    Plan plan;
+    int rc = make_plan(c->cfg, meshes, n, &plan);
+    if (rc != GP_OK) return rc;
+    reap_retired(c, false);
 
-    // tile spaces and capacities
-    std::vector<gp::MeshDesc> descs(n);
-    int64_t tri_tiles = 0, he_tiles = 0, cmp_tiles = 0, cap_tips = 0, out_bytes = 0, tmp_mesh = 0;
-    for (int i = 0; i < n; i++) {
-        const gp_mesh *m = meshes[i];
-        descs[i].nt = m->nt;
-        descs[i].nv = m->nv;
-        descs[i].tri_tile0 = (int32_t)tri_tiles;
-        descs[i].he_tile0 = (int32_t)he_tiles;
-        descs[i].cmp_tile0 = (int32_t)cmp_tiles;
-        tri_tiles += gp::tiles_for(m->nt, tt);
-        he_tiles += gp::tiles_for(3ll * m->nt, th);
-        cmp_tiles += gp::tiles_for(m->nt, tc);
-        cap_tips += m->nt / 2 + 2;   // tips are interior vertices: at most T/2 + 1
-        const int64_t nh = 3ll * m->nt;
-        out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(m->nt + 1) +
-                     arena_bytes<int32_t>(m->nt + 2);
-        tmp_mesh += arena_bytes<uint8_t>(align_up(m->nt + 4, 4)) + arena_bytes<uint8_t>(m->nt + 1);
+    // scratch: per call from the pool, or owned by a cached graph
+    const bool use_graph = (out_flags & GP_GRAPH) && !c->profile;
+    GraphEntry *ge = nullptr;
+    void *p_tmp = nullptr;
+    if (use_graph) {
+        rc = graph_entry(c, plan, &ge);
+        if (rc != GP_OK) return rc;
+    } else {
+        rc = c->pool.alloc(plan.tmp_bytes, &p_tmp);
+        if (rc != GP_OK) return rc;
     }
-    if (tri_tiles > 0x7fffffff || he_tiles > 0x7fffffff || cap_tips > (1ll << 30)) return GP_ERANGE;
-    const int64_t cap_cands = 2 * cap_tips, cap_fix = 2 * cap_tips;
-    const size_t tmp_bytes = (size_t)tmp_mesh + arena_bytes<gp::MeshDesc>(n) + arena_bytes<gp::RunCounters>(1) +
-                             arena_bytes<gp::MeshCounters>(n) + arena_bytes<gp::ListEntry>(cap_tips) +
-                             arena_bytes<gp::ListEntry>(cap_cands) + arena_bytes<gp::ListEntry>(cap_fix) +
-                             arena_bytes<uint64_t>(cmp_tiles);
-
     RunState *r = new (std::nothrow) RunState();
-    if (!r) return GP_ENOMEM;
+    if (!r) {
+        c->pool.release(p_tmp);
+        return GP_ENOMEM;
+    }
     r->ctx = c;
     r->nmesh = n;
-    void *p_tmp = nullptr;
-    int rc = c->pool.alloc((size_t)out_bytes, &r->out_block);
-    if (rc == GP_OK) rc = c->pool.alloc(tmp_bytes, &p_tmp);
-    reap_retired(c, false);
+    rc = c->pool.alloc(plan.out_bytes, &r->out_block);
     if (rc == GP_OK) {
         r->host_ctrs_bytes = sizeof(gp::MeshCounters) * n;
         r->host_ctrs = static_cast<gp::MeshCounters *>(pinned_take(c, r->host_ctrs_bytes));
@@ -665,25 +739,18 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         run_destroy(r);
         return rc;
     }
-    Arena ao{static_cast<char *>(r->out_block), (size_t)out_bytes, 0};
-    Arena at{static_cast<char *>(p_tmp), tmp_bytes, 0};
-    std::vector<gp_result *> res(n, nullptr);
-    gp::MeshDesc *d_descs = at.take<gp::MeshDesc>(n);
     gp::RunBuffers rb{};
-    rb.descs = d_descs;
-    rb.nmesh = n;
-    rb.tri_tiles = (int32_t)tri_tiles;
-    rb.he_tiles = (int32_t)he_tiles;
-    rb.cmp_tiles = (int32_t)cmp_tiles;
-    rb.rc = at.take<gp::RunCounters>(1);
-    rb.ctrs = at.take<gp::MeshCounters>(n);
-    rb.tips = at.take<gp::ListEntry>(cap_tips);
-    rb.cands = at.take<gp::ListEntry>(cap_cands);
-    rb.fixes = at.take<gp::ListEntry>(cap_fix);
-    rb.cap_tips = (int32_t)cap_tips;
-    rb.cap_cands = (int32_t)cap_cands;
-    rb.cap_fix = (int32_t)cap_fix;
-    rb.status = at.take<uint64_t>(cmp_tiles);
+    std::vector<uint8_t *> tflag(n), pl(n);
+    if (ge) {
+        rb = ge->rb;
+        tflag = ge->tflag;
+        pl = ge->pl;
+    } else {
+        layout_scratch(plan, p_tmp, meshes, &rb, tflag.data(), pl.data());
+    }
+    Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
+    std::vector<gp_result *> res(n, nullptr);
+    std::vector<gp::MeshDesc> descs = plan.descs;
     for (int i = 0; i < n; i++) {
         const gp_mesh *m = meshes[i];
         const int64_t nh = 3ll * m->nt;
@@ -715,22 +782,26 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         d.seeds = x->seeds;
         d.loop_off = x->loop_off;
         d.loop_he = x->loop_he;
-        d.tflag = at.take<uint8_t>(align_up(m->nt + 4, 4));
-        d.pl = at.take<uint8_t>(m->nt + 1);
+        d.tflag = tflag[i];
+        d.pl = pl[i];
         d.ctr = rb.ctrs + i;
     }
-    // descriptor table: pinned staging, stream-ordered copy
     hipStream_t s = c->stream;
     int err = GP_OK;
-    if (stage_to_device(c, d_descs, descs.data(), sizeof(gp::MeshDesc) * n) != hipSuccess) err = GP_EHIP;
-    if (err == GP_OK &&
-        gp::launch_pipeline(cfg, rb, s, c->profile ? profile_hook : nullptr, c) != hipSuccess)
+    if (stage_to_device(c, const_cast<gp::MeshDesc *>(rb.descs), descs.data(), sizeof(gp::MeshDesc) * n) !=
+        hipSuccess)
         err = GP_EHIP;
+    if (err == GP_OK) {
+        hipError_t e = ge ? hipGraphLaunch(ge->exec, s)
+                          : gp::launch_pipeline(c->cfg, rb, s, c->profile ? profile_hook : nullptr, c);
+        if (e != hipSuccess) err = GP_EHIP;
+    }
     if (err == GP_OK && (hipMemcpyAsync(r->host_ctrs, rb.ctrs, sizeof(gp::MeshCounters) * n,
                                         hipMemcpyDeviceToHost, s) != hipSuccess ||
                          hipEventRecord(r->done, s) != hipSuccess))
         err = GP_EHIP;
-    // temporaries go back to the pool; later users are ordered after this run
+    // per-call temporaries go back to the pool; later users are ordered after
+    // this run on the same stream
     c->pool.release(p_tmp);
     if (err != GP_OK) {
         (void)hipGetLastError();
@@ -757,12 +828,23 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     return GP_OK;
 }
 
+namespace {
+GraphCache &graphs_of(gp_ctx *c) {
+    if (!c->graphs) c->graphs = new GraphCache();
+    return *c->graphs;
+}
+}  // namespace
+
 int gpolylla_mesh(gp_ctx *c, const gp_mesh *m, uint32_t out_flags, gp_result **out) {
     if (!m) return GP_EINVAL;
     return gpolylla_mesh_batch(c, &m, 1, out_flags, out);
 }
 
 int gpolylla_result_info(gp_result *x, gp_result_info *info) {
+    if (x && info && x->host) {
+        *info = x->hinfo;
+        return GP_OK;
+    }
     if (!x || !info || !x->run) return GP_EINVAL;
     int st = run_sync(x->run);
     if (st != GP_OK) return st;
@@ -787,6 +869,15 @@ int gpolylla_result_copy(gp_result *x, int32_t *next, int32_t *prev, int32_t *se
     gp_result_info info;
     int st = gpolylla_result_info(x, &info);
     if (st != GP_OK) return st;
+    if (x->host) {
+        const size_t nh = (size_t)info.nh;
+        if (next && nh) std::memcpy(next, x->next_o, 4 * nh);
+        if (prev && nh) std::memcpy(prev, x->prev_o, 4 * nh);
+        if (seeds && info.npoly) std::memcpy(seeds, x->seeds, 4 * (size_t)info.npoly);
+        if (loop_off) std::memcpy(loop_off, x->loop_off, 4 * (size_t)(info.npoly + 1));
+        if (loop_he && info.nloop_he) std::memcpy(loop_he, x->loop_he, 4 * (size_t)info.nloop_he);
+        return GP_OK;
+    }
     DeviceGuard g(x->run->ctx->device);
     hipStream_t s = x->run->ctx->stream;
     const size_t nh = (size_t)info.nh;
@@ -802,7 +893,7 @@ int gpolylla_result_copy(gp_result *x, int32_t *next, int32_t *prev, int32_t *se
 }
 
 int gpolylla_result_device(gp_result *x, gp_result_dev *dev) {
-    if (!x || !dev || !x->run) return GP_EINVAL;
+    if (!x || !dev || !x->run || x->host) return GP_EINVAL;
     dev->next = x->next_o;
     dev->prev = x->prev_o;
     dev->seeds = x->seeds;
@@ -813,7 +904,11 @@ int gpolylla_result_device(gp_result *x, gp_result_dev *dev) {
 
 void gpolylla_result_free(gp_result *x) {
     if (!x) return;
-    run_unref(x->run);
+    if (x->host) {
+        if (x->on_free) x->on_free();
+    } else {
+        run_unref(x->run);
+    }
     delete x;
 }
 

@@ -1,0 +1,228 @@
+// Objects behind the opaque handles of include/gpolylla.h, shared by the
+// runtime (runtime.cpp) and the serving loop (serve.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gpolylla.h"
+#include "gp_internal.h"
+
+namespace gprt {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t n, size_t a = kAlign) { return (n + a - 1) / a * a; }
+
+// Device memory of one context.  Two modes:
+//  - caching (default): blocks are kept after release and handed out again
+//    for requests of up to 12.5% smaller size;
+//  - arena: one block reserved up front, allocations bump through it,
+//    release does nothing and reset() frees everything at once (the serving
+//    loop resets a lane's arena when the lane's batch is done).
+// All users of one pool run on one stream, so reuse after release (or after
+// a reset) is ordered after earlier work by the stream.
+class DevPool {
+  public:
+    size_t cap = 0;
+    size_t held = 0;
+    size_t in_use = 0;
+
+    int make_arena(size_t bytes) {
+        bytes = align_up(bytes);
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return GP_ENOMEM;
+        }
+        arena_ = static_cast<char *>(q);
+        arena_cap_ = bytes;
+        arena_off_ = 0;
+        held = bytes;
+        return GP_OK;
+    }
+    bool is_arena() const { return arena_ != nullptr; }
+    size_t arena_free() const { return arena_cap_ - arena_off_; }
+    void reset() {
+        arena_off_ = 0;
+        in_use = 0;
+    }
+
+    int alloc(size_t n, void **p) {
+        n = align_up(n ? n : kAlign);
+        if (arena_) {
+            if (arena_off_ + n > arena_cap_) return GP_ENOMEM;
+            *p = arena_ + arena_off_;
+            arena_off_ += n;
+            in_use += n;
+            return GP_OK;
+        }
+        auto it = free_.lower_bound(n);
+        if (it != free_.end() && it->first <= n + n / 8) {
+            *p = it->second;
+            in_use += it->first;
+            used_[*p] = it->first;
+            free_.erase(it);
+            return GP_OK;
+        }
+        if (cap && held + n > cap) trim();
+        if (cap && held + n > cap) return GP_ENOMEM;
+        void *q = nullptr;
+        if (hipMalloc(&q, n) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            if (hipMalloc(&q, n) != hipSuccess) {
+                (void)hipGetLastError();
+                return GP_ENOMEM;
+            }
+        }
+        held += n;
+        in_use += n;
+        used_[q] = n;
+        *p = q;
+        return GP_OK;
+    }
+    void release(void *p) {
+        if (!p || arena_) return;
+        auto it = used_.find(p);
+        if (it == used_.end()) return;
+        in_use -= it->second;
+        free_.emplace(it->second, p);
+        used_.erase(it);
+    }
+    void trim() {
+        for (auto &kv : free_) {
+            (void)hipFree(kv.second);
+            held -= kv.first;
+        }
+        free_.clear();
+    }
+    void destroy() {
+        trim();
+        for (auto &kv : used_) (void)hipFree(kv.first);
+        used_.clear();
+        if (arena_) (void)hipFree(arena_);
+        arena_ = nullptr;
+        held = in_use = 0;
+    }
+
+  private:
+    std::multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> used_;
+    char *arena_ = nullptr;
+    size_t arena_cap_ = 0, arena_off_ = 0;
+};
+
+// A bump arena carved out of one pool block.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, off = 0;
+    template <class T>
+    T *take(size_t count) {
+        size_t n = align_up(count * sizeof(T));
+        T *p = reinterpret_cast<T *>(base + off);
+        off += n;
+        return p;
+    }
+};
+
+template <class T>
+size_t arena_bytes(size_t count) {
+    return align_up(count * sizeof(T));
+}
+
+struct RunState;
+struct GraphCache;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// device bytes gpolylla_build_halfedges takes from the pool
+size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device);
+// device bytes gpolylla_mesh_batch takes from the pool for meshes of these sizes
+size_t batch_footprint(const gp::LaunchCfg &cfg, const int32_t *nts, int n);
+
+}  // namespace gprt
+
+struct gp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    gprt::DevPool pool;
+    gp::LaunchCfg cfg;
+    bool profile = false;
+    struct Pending {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare_events;
+    hipEvent_t open_ev[gp::K_COUNT] = {};
+    double kms[gp::K_COUNT] = {};
+    int64_t kcount[gp::K_COUNT] = {};
+    // pinned host memory: cached blocks, descriptor staging ring, and runs
+    // whose results were freed before their work finished
+    std::multimap<size_t, void *> pinned_free;
+    struct Slot {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+        hipEvent_t ev = nullptr;
+        bool armed = false;
+    };
+    Slot ring[4];
+    int ring_next = 0;
+    std::vector<gprt::RunState *> retired;
+    gprt::GraphCache *graphs = nullptr;
+};
+
+struct gp_mesh {
+    gp_ctx *ctx = nullptr;
+    int32_t nv = 0, nt = 0;
+    int64_t nflipped = 0;
+    int2 *xy = nullptr;
+    int32_t *org = nullptr;
+    int32_t *twin = nullptr;
+};
+
+namespace gprt {
+struct RunState {
+    gp_ctx *ctx = nullptr;
+    void *out_block = nullptr;        // outputs of every mesh of the run
+    gp::MeshCounters *host_ctrs = nullptr;  // pinned
+    size_t host_ctrs_bytes = 0;
+    int nmesh = 0;
+    hipEvent_t done = nullptr;
+    bool synced = false;
+    int status = GP_OK;
+    int refs = 0;
+};
+}  // namespace gprt
+
+// A result is either device-resident (run != nullptr: outputs in the run's
+// pool block) or host-resident (host == true: outputs in host memory that
+// on_free gives back; made by the serving loop).
+struct gp_result {
+    gprt::RunState *run = nullptr;
+    int index = 0;
+    int32_t nt = 0, nv = 0;
+    int64_t nflipped = 0;
+    int32_t *next_o = nullptr, *prev_o = nullptr, *seeds = nullptr, *loop_off = nullptr,
+            *loop_he = nullptr;
+    bool host = false;
+    gp_result_info hinfo{};
+    std::function<void()> on_free;
+};

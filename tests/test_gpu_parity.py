@@ -219,3 +219,32 @@ def test_build_errors_match_oracle(ctx, case):
     with pytest.raises(gp.GPolyllaError) as eg:
         ctx.build_halfedges(xy, tri)
     assert eg.value.code == eo.value.code
+
+
+def test_graph_replays_match_eager(ctx):
+    """The captured chain, replayed several times with eager runs and syncs in
+    between, gives the eager result every time (one mesh and a batch)."""
+    meshes = [W.jittered_grid(40, seed=71, warp=True), W.random_delaunay(4000, 72),
+              W.jittered_grid(9, seed=73)]
+    hs = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
+    eager = [ctx.mesh(h).copy() for h in hs]
+    keys = ("next", "prev", "seeds", "loop_off", "loop_he")
+    for rep in range(4):
+        say(f"[gpu] graph replay {rep}")
+        r = ctx.mesh(hs[0], gp.GP_GRAPH)
+        got = r.copy()
+        r.free()
+        for k in keys:
+            assert np.array_equal(got[k], eager[0][k]), (rep, k)
+        rs = ctx.mesh_batch(hs, gp.GP_GRAPH)
+        for i, rr in enumerate(rs):
+            got = rr.copy()
+            for k in keys:
+                assert np.array_equal(got[k], eager[i][k]), (rep, i, k)
+            rr.free()
+        # eager work and a sync between replays
+        e = ctx.mesh(hs[1])
+        e.free()
+        ctx.sync()
+    for h in hs:
+        h.free()

@@ -1,0 +1,92 @@
+"""Served meshing: every result equals the oracle's, and the same request
+gives the same result alone and inside a concurrent mix (integer outputs:
+tolerance zero)."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_14723_amd as gp
+from paper_2403_14723_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+KEYS = ("next", "prev", "seeds", "loop_off", "loop_he")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    out = [W.jittered_grid(n, seed=500 + n, warp=(n % 3 == 0)) for n in (1, 7, 30, 64, 99, 160, 257)]
+    out += [W.random_delaunay(2000, 501), W.random_delaunay(15000, 502)]
+    return out
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gp.Context(0)
+    yield c
+    c.close()
+
+
+def test_served_alone_equals_mix_and_oracle(ctx):
+    reqs = _requests()
+    with gp.Server(ctx, pool_bytes=2 << 30, max_batch=8, n_lanes=2) as srv:
+        say("[gpu] serve: one at a time")
+        alone = []
+        for m in reqs:
+            r = srv.wait(srv.submit(m.xy, m.tri))
+            alone.append(r.copy())
+            r.free()
+        say("[gpu] serve: concurrent mix from two threads")
+        tickets = [None] * len(reqs)
+
+        def client(idx):
+            for i in idx:
+                tickets[i] = srv.submit(reqs[i].xy, reqs[i].tri)
+
+        th = [threading.Thread(target=client, args=(range(k, len(reqs), 2),)) for k in (0, 1)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        mix = []
+        for t in tickets:
+            r = srv.wait(t, 60000)
+            mix.append(r.copy())
+            r.free()
+        st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    for m, a, b in zip(reqs, alone, mix):
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k]), (m.name, k)
+        o = oracle.polylla(m.xy, m.tri)
+        for k in KEYS:
+            assert np.array_equal(a[k], getattr(o, k)), (m.name, k)
+
+
+def test_served_errors(ctx):
+    with gp.Server(ctx, pool_bytes=64 << 20, max_batch=4, n_lanes=1) as srv:
+        say("[gpu] serve: bad request in a batch")
+        bad = srv.submit(np.array([[0, 0], [1, 1], [2, 2]]), np.array([[0, 1, 2]]))
+        good = W.jittered_grid(20, seed=9)
+        ok = srv.submit(good.xy, good.tri)
+        with pytest.raises(gp.GPolyllaError) as e:
+            srv.wait(bad)
+        assert e.value.code == gp.GP_EDEGEN
+        r = srv.wait(ok)
+        o = oracle.polylla(good.xy, good.tri)
+        assert np.array_equal(r.copy()["loop_he"], o.loop_he)
+        r.free()
+        say("[gpu] serve: request larger than a lane")
+        big = W.jittered_grid(1024, seed=1)
+        with pytest.raises(gp.GPolyllaError) as e:
+            srv.submit(big.xy, big.tri)
+        assert e.value.code == gp.GP_ETOOBIG
+        with pytest.raises(gp.GPolyllaError) as e:
+            srv.wait(12345678, 10)
+        assert e.value.code == gp.GP_EINVAL
