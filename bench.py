@@ -72,6 +72,106 @@ def cpu_baseline(mesh):
     }, res
 
 
+def bench_batched(gp, W, stream, steps):
+    """The 512-mesh batch: one batched run (graph replay) per step against 512
+    plain gpolylla_mesh calls per step, same meshes, same stream."""
+    import torch
+    meshes = W.batch_meshes(512, seed=3)
+    ctx = gp.Context(0, stream=stream.cuda_stream)
+    hs = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
+    T = sum(m.nt for m in meshes)
+    flags = gp.GP_ASYNC | gp.GP_GRAPH
+
+    def run_batched():
+        for r in ctx.mesh_batch(hs, flags):
+            r.free()
+
+    def run_plain():
+        for h in hs:
+            ctx.mesh(h, gp.GP_ASYNC).free()
+
+    out = {"meshes": len(meshes), "triangles": T}
+    for name, fn in (("batched", run_batched), ("plain", run_plain)):
+        for _ in range(2):
+            fn()
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) / steps * 1e3
+        ms = e0.elapsed_time(e1) / steps
+        out[f"{name}_ms"] = round(ms, 4)
+        out[f"{name}_wall_ms"] = round(wall, 4)
+        out[f"{name}_mtri_s"] = round(T / (max(ms, wall) * 1e-3) / 1e6, 1)
+    out["batched_over_plain"] = round(out["batched_mtri_s"] / out["plain_mtri_s"], 2)
+    for h in hs:
+        h.free()
+    ctx.close()
+    return out
+
+
+def bench_served(gp, W, n_req=2000, warm=64, cap_n=256, rhos=(0.5, 0.8)):
+    """Continuous-batching server: capacity from a closed loop, then Poisson
+    arrivals at rho * capacity; latency = submit -> result on the host."""
+    import queue
+    import threading
+    import numpy as np
+    reqs = W.served_requests(n_req)
+    mean_t = float(np.mean([m.nt for m in reqs]))
+    ctx = gp.Context(0)
+    srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=3)
+
+    def closed_loop(n):
+        ts = [srv.submit(reqs[i % n_req].xy, reqs[i % n_req].tri) for i in range(n)]
+        for t in ts:
+            srv.wait(t).free()
+
+    closed_loop(warm)
+    srv.reset_stats()
+    closed_loop(cap_n)
+    cap = srv.stats()["mtri_s"]
+    out = {"requests": n_req, "mean_triangles": round(mean_t), "distinct_meshes": len({id(m) for m in reqs}),
+           "capacity_mtri_s": round(cap, 1), "lanes": 3, "max_batch": 32, "runs": []}
+    for k, rho in enumerate(rhos):
+        lam = rho * cap * 1e6 / mean_t
+        gaps = W.poisson_gaps(n_req, lam, seed=5 + k)
+        srv.reset_stats()
+        tq: queue.Queue = queue.Queue()
+
+        def waiter():
+            while True:
+                t = tq.get()
+                if t is None:
+                    return
+                srv.wait(t).free()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        at = t0
+        for i in range(n_req):
+            at += gaps[i]
+            d = at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tq.put(srv.submit(reqs[i].xy, reqs[i].tri))
+        tq.put(None)
+        th.join()
+        st = srv.stats()
+        out["runs"].append({"rho": rho, "rate_per_s": round(lam, 1), "completed": st["completed"],
+                            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                            "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                            "mtri_s": round(st["mtri_s"], 1), "batches": st["batches"]})
+    srv.stop()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +180,8 @@ def main():
     ap.add_argument("--workload", default="plain_4096x4096_warped", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--check", action="store_true", help="compare the GPU result with the oracle")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--served-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the pipeline runs on a single device); "
@@ -178,6 +280,15 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     value = nt / (ms_per_step * 1e-3) / 1e6
 
+    batched = served = None
+    if not args.no_forms:
+        log("[bench] batched vs plain (512 meshes)")
+        batched = bench_batched(gp, W, stream, max(3, args.steps // 4))
+        log(f"[bench] {batched}")
+        log("[bench] served (Poisson arrivals)")
+        served = bench_served(gp, W, n_req=args.served_requests)
+        log(f"[bench] {served}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline (single thread)")
@@ -207,6 +318,8 @@ def main():
         "kernels": kernels,
         "separate": {"h2d_ms": round(h2d_ms, 3), "build_ms": round(build_ms, 3), "d2h_ms": round(d2h_ms, 3),
                      "with_copies_mtri_s": round(nt / ((h2d_ms + build_ms + ms_per_step + d2h_ms) * 1e-3) / 1e6, 2)},
+        "batched": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     if check is not None:

@@ -221,39 +221,37 @@ def batch_meshes(count: int = 512, seed: int = 3, smin: int = 16, smax: int = 51
     return out
 
 
-@dataclass(frozen=True)
-class Request:
-    arrival_s: float
-    mesh: Mesh
-
-
-def request_stream(count: int, rate_hz: float, seed: int = 4, tmin: float = 1e3,
-                   tmax: float = 4e6, warp_frac: float = 0.3) -> list[Request]:
-    """Poisson arrivals at rate_hz; triangle count log-uniform in [tmin, tmax];
-    side s = round(sqrt(T/2)); a warp_frac share of requests is warped."""
+def served_requests(count: int, seed: int = 4, tmin: float = 1e3, tmax: float = 4e6,
+                    warp_frac: float = 0.3, distinct: int = 96) -> list[Mesh]:
+    """Request meshes for the served workload: triangle count log-uniform in
+    [tmin, tmax] (side s = round(sqrt(T/2))), a warp_frac share warped.  To
+    keep generation bounded the side is snapped to one of `distinct`
+    log-spaced values and each (side, warp) mesh is generated once and shared
+    by every request that draws it."""
     if not (0 <= seed < 16 and count <= 1 << 16):
         raise ValueError("seed must be < 16 and count <= 65536")
     k = np.arange(count, dtype=np.uint64)
-    u_gap = uniform01(seed, _S_REQ, k * np.uint64(4))
     u_t = uniform01(seed, _S_REQ, k * np.uint64(4) + np.uint64(1))
     u_w = uniform01(seed, _S_REQ, k * np.uint64(4) + np.uint64(2))
-    gaps = -np.log1p(-u_gap) / rate_hz
-    arrivals = np.cumsum(gaps)
-    tri = np.exp(np.log(tmin) + u_t * (np.log(tmax) - np.log(tmin)))
-    sides = np.maximum(1, np.rint(np.sqrt(tri / 2.0))).astype(int)
+    lo, hi = np.log(np.sqrt(tmin / 2.0)), np.log(np.sqrt(tmax / 2.0))
+    side_f = np.exp(0.5 * (np.log(tmin) + u_t * (np.log(tmax) - np.log(tmin))) - 0.5 * np.log(2.0))
+    grid = np.exp(np.linspace(lo, hi, distinct))
+    idx = np.clip(np.rint((np.log(side_f) - lo) / (hi - lo) * (distinct - 1)).astype(int), 0, distinct - 1)
+    sides = np.maximum(1, np.rint(grid[idx])).astype(int)
+    warped = u_w < warp_frac
+    cache: dict = {}
     out = []
     for r in range(count):
-        sub = (seed << 16) | r
-        m = jittered_grid(int(sides[r]), seed=sub, warp=bool(u_w[r] < warp_frac),
-                     name=f"req{r}_s{int(sides[r])}")
-        out.append(Request(float(arrivals[r]), m))
+        key = (int(sides[r]), bool(warped[r]))
+        if key not in cache:
+            sub = (seed << 16) | (int(idx[r]) * 2 + int(warped[r]))
+            cache[key] = jittered_grid(key[0], seed=sub, warp=key[1], name=f"req_s{key[0]}{'w' if key[1] else ''}")
+        out.append(cache[key])
     return out
 
 
-def request_sizes(count: int, seed: int = 4, tmin: float = 1e3, tmax: float = 4e6) -> np.ndarray:
-    """Triangle counts of the first `count` requests of request_stream."""
+def poisson_gaps(count: int, rate_hz: float, seed: int = 4) -> np.ndarray:
+    """Exponential inter-arrival gaps (seconds) of a Poisson process."""
     k = np.arange(count, dtype=np.uint64)
-    u_t = uniform01(seed, _S_REQ, k * np.uint64(4) + np.uint64(1))
-    tri = np.exp(np.log(tmin) + u_t * (np.log(tmax) - np.log(tmin)))
-    sides = np.maximum(1, np.rint(np.sqrt(tri / 2.0))).astype(int)
-    return 2 * sides * sides
+    u = uniform01(seed, _S_REQ, k * np.uint64(4))
+    return -np.log1p(-u) / rate_hz
