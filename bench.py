@@ -41,13 +41,12 @@ def algorithmic_bytes(nt, nv, npoly, nloop):
 
 
 def kernel_bytes(name, nt, nv, npoly, nloop):
-    """Algorithmic bytes of one launch of the streaming kernels (see DESIGN.md).
+    """Algorithmic bytes of one launch of the streaming kernels.
     The list-driven kernels (k_repair, k_fixup, k_walk, k_emit) touch only the
     few loops and vertices on their lists and are not roofline candidates."""
     return {
-        "k_label": 12 * nt + 8 * nv + 2 * nt,                 # org, xy -> tflag, pl
-        "k_frontier": 12 * nt + 2 * nt,                       # twin, tflag -> tflag
-        "k_relink": 12 * nt + nt + 24 * nt,                   # twin, tflag -> next, prev
+        "k_label": 12 * nt + 8 * nv + nt,                     # org, xy -> tflag
+        "k_relink": 12 * nt + nt + 24 * nt + 2 * nt,          # twin, tflag -> next, prev, tflag, pl
         "k_compact": 2 * nt + 8 * npoly + 4 * nloop,          # pl, tflag -> seeds, loop_off, loop_he
     }.get(name)
 
@@ -74,10 +73,16 @@ def cpu_baseline(mesh):
 
 def bench_batched(gp, W, stream, steps):
     """The 512-mesh batch: one batched run (graph replay) per step against 512
-    plain gpolylla_mesh calls per step, same meshes, same stream."""
+    plain gpolylla_mesh calls per step, same meshes, same stream.  The launch
+    shapes come from the autotuner (its search is timed apart); the batch is
+    also timed with the default shapes."""
     import torch
+    from paper_2403_14723_amd import autotune
     meshes = W.batch_meshes(512, seed=3)
+    tuned = autotune.tune(meshes, log=log)
+    log(f"[bench] tuned {tuned['spec']} in {tuned['seconds']:.1f}s (cached: {tuned['cached']})")
     ctx = gp.Context(0, stream=stream.cuda_stream)
+    default_spec = ctx.launch()
     hs = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
     T = sum(m.nt for m in meshes)
     flags = gp.GP_ASYNC | gp.GP_GRAPH
@@ -90,8 +95,11 @@ def bench_batched(gp, W, stream, steps):
         for h in hs:
             ctx.mesh(h, gp.GP_ASYNC).free()
 
-    out = {"meshes": len(meshes), "triangles": T}
-    for name, fn in (("batched", run_batched), ("plain", run_plain)):
+    out = {"meshes": len(meshes), "triangles": T, "default_launch": default_spec,
+           "tuned_launch": tuned["spec"], "tune_s": round(tuned["seconds"], 2)}
+    for name, fn, spec in (("batched_default", run_batched, default_spec), ("batched", run_batched, tuned["spec"]),
+                           ("plain", run_plain, tuned["spec"])):
+        ctx.set_launch(spec)
         for _ in range(2):
             fn()
         ctx.sync()
@@ -295,7 +303,7 @@ def main():
         cpu, _ = cpu_baseline(mesh)
 
     line = {
-        "metric": "Mtri/s meshed on-device (label->relink->walk->repair); batched vs plain; p99 lat",
+        "metric": "Mtri/s meshed on-device (label\u2192relink\u2192walk\u2192repair); batched vs plain; p99 lat",
         "value": round(value, 2),
         "unit": "Mtri/s",
         "n_gpus": 1,

@@ -112,6 +112,27 @@ int gpolylla_ctx_pool_bytes(const gp_ctx *ctx, size_t *held, size_t *in_use);
 int gpolylla_ctx_kernel_ms(gp_ctx *ctx, const char **names, double *avg_ms, int64_t *launches, int cap);
 void gpolylla_ctx_kernel_reset(gp_ctx *ctx);
 
+/* Launch shapes of the pipeline kernels (the autotuner's interface; no
+ * passage of the paper fixes them).  spec is a comma-separated list of
+ * "kernel=BxI" entries, any subset in any order:
+ *   label=BxI, relink=BxI, compact=BxI   B threads per block (64..1024, a
+ *                                        multiple of 64), I items per thread
+ *                                        (1, 2, 4 or 8)
+ *   persist=BxN                          the list-driven kernels: B threads
+ *                                        per block, N blocks (1..65536)
+ * Tiles larger than a kernel's LDS staging allows (label 4096, relink 1024,
+ * compact 2048 triangles) are reduced by halving I.  Results never depend on
+ * the shapes.  Applies to runs started after the call; runs already queued
+ * keep their shapes, and captured graphs are kept per shape.  Not to be
+ * called concurrently with other calls on the same context.
+ * Errors: GP_EINVAL for a null argument or any malformed entry, in which case
+ * nothing changes. */
+int gpolylla_ctx_set_launch(gp_ctx *ctx, const char *spec);
+/* Writes the current shapes as a NUL-terminated spec of the form above into
+ * buf (truncated to cap - 1 characters; buf may be NULL when cap is 0).
+ * Returns the buffer size the whole spec needs (> 0), or GP_EINVAL. */
+int gpolylla_ctx_get_launch(const gp_ctx *ctx, char *buf, int32_t cap);
+
 /* ---- build -------------------------------------------------------------- */
 
 /*

@@ -92,6 +92,8 @@ def _load():
                                                   ctypes.POINTER(ctypes.c_double),
                                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
         "gpolylla_ctx_kernel_reset": (None, [_P]),
+        "gpolylla_ctx_set_launch": (ctypes.c_int, [_P, ctypes.c_char_p]),
+        "gpolylla_ctx_get_launch": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int32]),
         "gpolylla_build_halfedges": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                                     ctypes.c_uint32, ctypes.POINTER(_P)]),
         "gpolylla_mesh_copy": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -131,6 +133,7 @@ def exported_symbols() -> list[str]:
 
 _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", "gpolylla_ctx_pool_bytes",
             "gpolylla_ctx_sync", "gpolylla_ctx_kernel_ms", "gpolylla_ctx_kernel_reset",
+            "gpolylla_ctx_set_launch", "gpolylla_ctx_get_launch",
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
             "gpolylla_result_device", "gpolylla_result_free", "gpolylla_serve_start", "gpolylla_serve_submit",
@@ -176,6 +179,20 @@ def gpolylla_ctx_kernel_ms(ctx) -> dict:
 
 def gpolylla_ctx_kernel_reset(ctx):
     _load().gpolylla_ctx_kernel_reset(ctx)
+
+
+def gpolylla_ctx_set_launch(ctx, spec: str):
+    _check(_load().gpolylla_ctx_set_launch(ctx, spec.encode()), f"gpolylla_ctx_set_launch({spec!r})")
+
+
+def gpolylla_ctx_get_launch(ctx) -> str:
+    lib = _load()
+    n = lib.gpolylla_ctx_get_launch(ctx, None, 0)
+    if n < 0:
+        _check(n, "gpolylla_ctx_get_launch")
+    buf = ctypes.create_string_buffer(n)
+    _check(min(0, lib.gpolylla_ctx_get_launch(ctx, buf, n)), "gpolylla_ctx_get_launch")
+    return buf.value.decode()
 
 
 def gpolylla_ctx_pool_bytes(ctx) -> tuple[int, int]:
@@ -410,6 +427,12 @@ class Context:
 
     def kernel_reset(self):
         gpolylla_ctx_kernel_reset(self.handle)
+
+    def set_launch(self, spec: str):
+        gpolylla_ctx_set_launch(self.handle, spec)
+
+    def launch(self) -> str:
+        return gpolylla_ctx_get_launch(self.handle)
 
     def pool_bytes(self):
         return gpolylla_ctx_pool_bytes(self.handle)

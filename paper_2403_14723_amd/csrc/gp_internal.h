@@ -87,7 +87,7 @@ constexpr int kStripePad = 32;   // counters 128 bytes apart: one cache line eac
 
 struct LaunchCfg {
     int block_label = 256, items_label = 4;
-    int block_relink = 256, items_relink = 2;     // k_frontier and k_relink (tile <= 1024 triangles)
+    int block_relink = 256, items_relink = 2;     // k_relink (tile <= 1024 triangles)
     int block_compact = 512, items_compact = 4;   // tile <= 2048 triangles (LDS 20 B each)
     int persistent_blocks = 1024;
     int block_persistent = 256;
@@ -113,7 +113,7 @@ struct RunBuffers {
     int32_t emit_cap;        // per stripe
 };
 
-enum KernelId { K_INIT = 0, K_LABEL, K_FRONTIER, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_EMIT, K_COUNT };
+enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.

@@ -10,10 +10,10 @@
 // regrouped so that every step reads its inputs contiguously):
 //   k_init      clears run counters, per-mesh counters and scan tile status
 //   k_label     longest edge of every triangle (Section 6.1, Algorithm 8)
-//   k_frontier  frontier bits of every half-edge (Section 6.2, Algorithm 9)
-//               and the seed bit of terminal edges (Section 6.3, Algorithm 10)
-//   k_relink    next/prev of every frontier half-edge by turning around its
-//               target / origin (Section 6.5, Algorithm 12); barrier tips
+//   k_relink    frontier bits of every half-edge (Section 6.2, Algorithm 9),
+//               the seed bit of terminal edges (Section 6.3, Algorithm 10),
+//               then next/prev of every frontier half-edge by turning around
+//               its target / origin (Section 6.5, Algorithm 12); barrier tips
 //   k_repair    middle edge at every barrier tip (Section 6.4, Algorithm 11)
 //   k_fixup     next/prev again around both ends of every new frontier edge
 //   k_walk      for every seed k_relink left open and every seed made by the
@@ -36,21 +36,35 @@
 
 namespace gp {
 
-const char *const kKernelNames[K_COUNT] = {"k_init",   "k_label", "k_frontier", "k_relink", "k_repair",
-                                           "k_fixup",  "k_walk",  "k_compact",  "k_emit"};
+const char *const kKernelNames[K_COUNT] = {"k_init", "k_label",   "k_relink", "k_repair", "k_fixup",
+                                           "k_walk", "k_compact", "k_emit"};
 
 constexpr uint32_t kSeedBit = 1u << 5;
+
+// The mesh arrays reached through the descriptor table live in global
+// memory; saying so lets the compiler use global (not flat) loads and stores
+// with a scalar base and a 32-bit offset.
+#define GLOBAL __attribute__((address_space(1)))
+typedef GLOBAL const int32_t *gcint;
+typedef GLOBAL int32_t *gint;
+typedef GLOBAL const uint8_t *gcu8;
+typedef GLOBAL uint8_t *gu8;
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef GLOBAL const v2i *gcv2i;
 
 // ---------------------------------------------------------------------------
 // half-edge queries (implicit triangle layout, Section 4.2)
 // ---------------------------------------------------------------------------
 
+// (h >= 0 everywhere these are used; unsigned division by 3 is a multiply)
+__device__ __forceinline__ int tri_of(int h) { return (int)((unsigned)h / 3u); }
 __device__ __forceinline__ int he_next(int h) {
-    int t = h / 3;
+    const int t = tri_of(h);
     return (h - 3 * t == 2) ? h - 2 : h + 1;
 }
 __device__ __forceinline__ int he_prev(int h) {
-    int t = h / 3;
+    const int t = tri_of(h);
     return (h - 3 * t == 0) ? h + 2 : h - 1;
 }
 
@@ -237,19 +251,19 @@ __device__ __forceinline__ int striped_index(const int *s_pref, int cap, int g) 
 }
 
 // Copies n ints from global src to LDS dst; src and dst 16-byte aligned.
-__device__ __forceinline__ void load_to_lds(int *dst, const int32_t *__restrict__ src, int n) {
+__device__ __forceinline__ void load_to_lds(int *dst, gcint src, int n) {
     const int B = blockDim.x, tid = threadIdx.x;
-    const int4 *s4 = reinterpret_cast<const int4 *>(src);
-    int4 *d4 = reinterpret_cast<int4 *>(dst);
+    GLOBAL const v4i *s4 = reinterpret_cast<GLOBAL const v4i *>(src);
+    v4i *d4 = reinterpret_cast<v4i *>(dst);
     for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
     for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
 }
 
 // Copies n ints from LDS src to global dst; both 16-byte aligned.
-__device__ __forceinline__ void store_from_lds(int32_t *dst, const int *src, int n) {
+__device__ __forceinline__ void store_from_lds(gint dst, const int *src, int n) {
     const int B = blockDim.x, tid = threadIdx.x;
-    const int4 *s4 = reinterpret_cast<const int4 *>(src);
-    int4 *d4 = reinterpret_cast<int4 *>(dst);
+    const v4i *s4 = reinterpret_cast<const v4i *>(src);
+    GLOBAL v4i *d4 = reinterpret_cast<GLOBAL v4i *>(dst);
     for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
     for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
 }
@@ -294,18 +308,19 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
     const MeshDesc &d = descs[mi];
     const int nt = d.nt;
     const int base = (tile - d.tri_tile0) * B * ITEMS;
-    const int2 *__restrict__ xy = d.xy;
+    const gcv2i xy = (gcv2i)(d.xy);
     // the tile's corners in one contiguous load; item j of this thread is
     // triangle base + j*B + tid
     const int cnt_all = min(B * ITEMS, nt - base);
-    if (cnt_all > 0) load_to_lds(s_org, d.org + 3 * (size_t)base, 3 * cnt_all);
+    if (cnt_all > 0) load_to_lds(s_org, (gcint)(d.org) + 3 * (size_t)base, 3 * cnt_all);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
         const int t = base + lt;
         if (t >= nt) break;
-        const int2 p0 = xy[s_org[3 * lt]], p1 = xy[s_org[3 * lt + 1]], p2 = xy[s_org[3 * lt + 2]];
+        const v2i q0 = xy[s_org[3 * lt]], q1 = xy[s_org[3 * lt + 1]], q2 = xy[s_org[3 * lt + 2]];
+        const int2 p0 = make_int2(q0.x, q0.y), p1 = make_int2(q1.x, q1.y), p2 = make_int2(q2.x, q2.y);
         const long long l0 = sq_len(p0, p1), l1 = sq_len(p1, p2), l2 = sq_len(p2, p0);
         long long m = l0 > l1 ? l0 : l1;
         m = m > l2 ? m : l2;
@@ -329,69 +344,117 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
             }
             atomicAdd(&d.ctr->nties, 1);
         }
-        d.tflag[t] = (uint8_t)best;
-        d.pl[t] = 0;
+        ((gu8)d.tflag)[t] = (uint8_t)best;
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_frontier: frontier bits and seed bit from the longest-edge labels
-// ---------------------------------------------------------------------------
-
-template <int ITEMS>
-__global__ void __launch_bounds__(1024) k_frontier(const MeshDesc *__restrict__ descs, int nmesh) {
-    extern __shared__ int4 lds_raw[];
-    int *s_tw = reinterpret_cast<int *>(lds_raw);
-    const int B = blockDim.x, tid = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int mi = find_mesh<1>(descs, nmesh, tile);
-    const MeshDesc &d = descs[mi];
-    const int nt = d.nt;
-    const int base = (tile - d.he_tile0) * B * ITEMS;
-    const int cnt_all = min(B * ITEMS, nt - base);
-    if (cnt_all > 0) load_to_lds(s_tw, d.twin + 3 * (size_t)base, 3 * cnt_all);
-    __syncthreads();
-    uint8_t *__restrict__ tflag = d.tflag;
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const int lt = j * B + tid;
-        const int t = base + lt;
-        if (t >= nt) break;
-        const int tw[3] = {s_tw[3 * lt], s_tw[3 * lt + 1], s_tw[3 * lt + 2]};
-        // only bits 0-1 of the neighbours are read; they do not change here
-        const uint32_t L = tflag[t] & 3u;
-        uint32_t out = L;
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            bool twin_long = false;
-            if (tw[i] >= 0) {
-                const int tg = tw[i] / 3;
-                twin_long = (int)(tflag[tg] & 3u) == tw[i] - 3 * tg;
-            }
-            // frontier: boundary, or the longest edge of neither triangle
-            if (tw[i] < 0 || ((int)L != i && !twin_long)) out |= 1u << (2 + i);
-            // terminal edge: longest on both sides (the lower half-edge holds
-            // the seed), or longest and on the boundary
-            if ((int)L == i && (tw[i] < 0 || (twin_long && 3 * t + i < tw[i]))) out |= kSeedBit;
-        }
-        tflag[t] = (uint8_t)out;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_relink: next/prev of every frontier half-edge, barrier tips
+// k_relink: frontier and seed bits, next/prev of every frontier half-edge,
+// barrier tips
 //
-// One thread per triangle.  Twins are loaded and next/prev stored through
-// LDS so the global accesses are contiguous.  The first candidate of each
-// turn is a half-edge of the same triangle; the second is in the neighbour
-// across the crossed edge, whose label was loaded with the others, so most
-// turns need no load beyond the four labels.
+// One thread per triangle.  Phase 1 derives each triangle's frontier bits
+// and seed bit from its own longest-edge label and its neighbours' (Section
+// 6.2-6.3) and keeps the byte in LDS.  Phase 2 turns around the ends of every
+// frontier half-edge (Section 6.5): a candidate in the tile reads its
+// frontier bit from LDS; one outside derives it from the longest-edge labels,
+// which no kernel changes during this pass (the tile's label bytes are
+// written back with their longest-edge bits unchanged).  Twins, next/prev and
+// the label and loop bytes move through LDS, so global accesses are
+// contiguous.
 // ---------------------------------------------------------------------------
+
+// Loop byte of the minimum's triangle: (min(len, kPlMax) << 2) | local
+// index of the minimum.  Length code 1 (no loop is that short) marks a loop
+// of four whose second triangle is t + 1; its low bits then hold the local
+// index of that triangle's terminal edge, and the minimum is the lower of
+// the two frontier half-edges of t.
+__device__ __forceinline__ uint8_t loop_code(int mn, int len) {
+    return (uint8_t)(((len < kPlMax ? len : kPlMax) << 2) | (mn % 3));
+}
+constexpr int kPlQuadNext = 1;
 
 // Records loop (minimum mn, length len) in the byte of the minimum's triangle.
 __device__ __forceinline__ void record_loop(const MeshDesc &d, int mn, int len) {
-    const int tm = mn / 3;
-    d.pl[tm] = (uint8_t)(((len < kPlMax ? len : kPlMax) << 2) | (mn - 3 * tm));
+    ((gu8)d.pl)[tri_of(mn)] = loop_code(mn, len);
+}
+
+// Copies n bytes from LDS src to global dst; both 4-byte aligned.
+__device__ __forceinline__ void store_bytes_from_lds(gu8 dst, const uint8_t *src, int n) {
+    const int B = blockDim.x, tid = threadIdx.x;
+    const uint32_t *s4 = reinterpret_cast<const uint32_t *>(src);
+    GLOBAL uint32_t *d4 = reinterpret_cast<GLOBAL uint32_t *>(dst);
+    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
+    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
+}
+
+// Frontier test of half-edge c during k_relink.  Lc is the longest-edge label
+// of c's triangle, or -1 when it has not been loaded.
+struct TileLabels {
+    gcint twin;
+    gcu8 tflag;                          // longest-edge bits (0-1) only are read
+    const int *s_tw;                     // the tile's twins
+    const uint8_t *s_f;                  // the tile's label bytes, frontier bits set
+    int base, cnt;                       // the tile's triangles [base, base + cnt)
+};
+
+// One step of a turn around a vertex at candidate c (Lc: the longest-edge
+// label of c's triangle, or -1 when not loaded).  Returns 1 when c is a
+// frontier half-edge (the turn ends there), 0 after moving c to the next
+// candidate (next: c <- next(twin(c)), else c <- prev(twin(c))), -1 when the
+// mesh is inconsistent.
+__device__ __forceinline__ int turn_step(const TileLabels &T, int &c, int &Lc, bool next) {
+    const int tc = tri_of(c), lc = c - 3 * tc, kk = tc - T.base;
+    int g, Lg = -1;
+    if ((unsigned)kk < (unsigned)T.cnt) {
+        if (fbit(T.s_f[kk], lc)) return 1;
+        g = T.s_tw[3 * kk + lc];
+        if (g < 0) return -1;   // a non-frontier edge is interior
+    } else {
+        g = T.twin[c];
+        if (g < 0) return 1;   // boundary
+        if (Lc < 0) Lc = (int)(T.tflag[tc] & 3u);
+        if (Lc != lc) {   // c is not its triangle's longest edge
+            const int tg = tri_of(g);
+            Lg = (int)(T.tflag[tg] & 3u);
+            if (Lg != g - 3 * tg) return 1;   // nor is twin(c)
+        }
+    }
+    c = next ? he_next(g) : he_prev(g);
+    Lc = Lg;
+    return 0;
+}
+
+// The whole turn from candidate c: the frontier half-edge it ends at, or -1.
+__device__ __forceinline__ int run_turn(const TileLabels &T, int c, int Lc, bool next) {
+    for (int k = 0; k < kRotGuard; k++) {
+        const int r = turn_step(T, c, Lc, next);
+        if (r != 0) return r > 0 ? c : -1;
+    }
+    return -1;
+}
+
+// Appends barrier tip he of mesh mi to the tip list (tips are rare).
+__device__ __forceinline__ void push_tip(RunCounters *rc, ListEntry *tips, int cap_tips, const MeshDesc &d, int mi,
+                                         int he, bool &err) {
+    const int slot = atomicAdd(&rc->ntips, 1);
+    if (slot < cap_tips) {
+        tips[slot].mesh = mi;
+        tips[slot].he = he;
+        atomicAdd(&d.ctr->ntips, 1);
+    } else {
+        err = true;
+    }
+}
+
+// Frontier bit of half-edge c of a triangle outside the tile whose
+// longest-edge label is Lc.
+__device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc) {
+    const int tc = c / 3, lc = c - 3 * tc;
+    if (Lc == lc) return false;
+    const int g = T.twin[c];
+    if (g < 0) return true;
+    const int tg = g / 3;
+    return (int)(T.tflag[tg] & 3u) != g - 3 * tg;
 }
 
 template <int ITEMS>
@@ -401,90 +464,174 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     extern __shared__ int4 lds_raw[];
     int *lds = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x, TB = B * ITEMS;
-    int *s_nx = lds, *s_pv = lds + 3 * TB;
+    int *s_tw = lds, *s_nx = lds + 3 * TB, *s_pv = lds + 6 * TB;
+    uint8_t *s_f = reinterpret_cast<uint8_t *>(lds + 9 * TB);   // label bytes
+    uint8_t *s_pl = s_f + TB;                                   // loop bytes
+    int *s_q = reinterpret_cast<int *>(s_pl + TB);              // queued turns, 2 ints each
+    const int qcap = TB / 2;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<1>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
     const int nt = d.nt;
-    const int32_t *__restrict__ twin = d.twin;
-    uint8_t *__restrict__ tflag = d.tflag;
+    const gcint twin = (gcint)(d.twin);
+    const gu8 tflag = (gu8)(d.tflag);
     const int base = (tile - d.he_tile0) * TB;
     const int cnt = min(TB, nt - base);
-    // every load of every item first (twins, own label, neighbour labels),
-    // so the lane keeps all of them in flight together
+    if (cnt <= 0) return;   // an empty mesh's tile (the whole block)
+    load_to_lds(s_tw, twin + 3 * (size_t)base, 3 * cnt);
+    __syncthreads();
+    // phase 1: labels of the triangle and its neighbours -> frontier, seed.
+    // Every load is issued unconditionally (indices clamped to 0, results
+    // masked after) so that all of them are in flight together.
     int tw[ITEMS][3];
     uint32_t f[ITEMS], fn[ITEMS][3];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        const int t = base + j * B + tid;
-        const bool ok = t < nt;
+        const int lt = j * B + tid;
+        const bool ok = lt < cnt;
 #pragma unroll
-        for (int i = 0; i < 3; i++) tw[j][i] = ok ? twin[3 * t + i] : -1;
+        for (int i = 0; i < 3; i++) {
+            const int g = s_tw[3 * lt + i];   // within the LDS tile; masked below
+            tw[j][i] = ok ? g : -1;
+        }
+        f[j] = tflag[base + (ok ? lt : 0)];
+#pragma unroll
+        for (int i = 0; i < 3; i++) fn[j][i] = tflag[tri_of(tw[j][i] < 0 ? 0 : tw[j][i])];
     }
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        const int t = base + j * B + tid;
-        f[j] = t < nt ? tflag[t] : 0u;
-#pragma unroll
-        for (int i = 0; i < 3; i++) fn[j][i] = tw[j][i] >= 0 ? tflag[tw[j][i] / 3] : 0u;
-    }
-    bool err = false;
-    int tipmask = 0;    // bit 3*j+i: half-edge i of item j ends at a barrier tip
-    int openmask = 0;   // bit j: item j holds a seed whose loop k_walk must walk
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
-        if (lt >= cnt) continue;
+        const int t = base + lt;
+        const uint32_t L = f[j] & 3u;
+        uint32_t out = L;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int g = tw[j][i];
+            fn[j][i] = g >= 0 ? fn[j][i] & 3u : 0u;
+            const bool twin_long = g >= 0 && (int)fn[j][i] == g - 3 * tri_of(g);
+            // frontier: boundary, or the longest edge of neither triangle
+            out |= (g < 0 || ((int)L != i && !twin_long)) ? 1u << (2 + i) : 0u;
+            // terminal edge: longest on both sides (the lower half-edge holds
+            // the seed), or longest and on the boundary
+            out |= ((int)L == i && (g < 0 || (twin_long && 3 * t + i < g))) ? kSeedBit : 0u;
+        }
+        f[j] = lt < cnt ? out : 0u;
+        if (lt < cnt) s_f[lt] = (uint8_t)out;
+    }
+    __syncthreads();
+    // phase 2: next'/prev' of every frontier half-edge.  The next (previous)
+    // edge in the triangle is taken when it is frontier itself; otherwise the
+    // turn continues in the neighbour across it.  A triangle has at most one
+    // frontier half-edge followed by a non-frontier one and at most one
+    // preceded by one, so each item has at most two turns; nearly all of
+    // them end at their first candidate.  The common path is straight-line
+    // code; only turns that go on, and candidates outside the tile, branch.
+    const TileLabels T = {twin, tflag, s_tw, s_f, base, cnt};
+    bool err = false;
+    int openmask = 0;   // bit j: item j holds a seed whose loop k_walk must walk
+    uint32_t pend = 0;  // bit 2j (2j+1): the next' (prev') turn of item j goes on
+    int cur[2 * ITEMS], lab[2 * ITEMS], src[2 * ITEMS];   // turn state; src: the
+                                                          // local index of the half-edge
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;   // lt >= cnt: f[j] == 0, so nothing is queued
+        const int h0 = 3 * (base + lt);
+        const uint32_t F3 = (f[j] >> 2) & 7u;
+        const uint32_t rn = ((F3 >> 1) | (F3 << 2)) & 7u;   // bit i: edge i+1 frontier
+        const uint32_t rp = ((F3 << 1) | (F3 >> 2)) & 7u;   // bit i: edge i-1 frontier
+        const uint32_t mn = F3 & ~rn, mp = F3 & ~rp;        // at most one bit each
+        // in-triangle values (the turn's slot is overwritten when it ends);
+        // entries past cnt are never stored
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            s_nx[3 * lt + i] = ((F3 & rn) >> i) & 1u ? h0 + (i == 2 ? 0 : i + 1) : -1;
+            s_pv[3 * lt + i] = ((F3 & rp) >> i) & 1u ? h0 + (i == 0 ? 2 : i - 1) : -1;
+        }
+        // next' turn: from the frontier half-edge na, across x = next(na)
+        const int na = mn ? __builtin_ctz(mn) : 0, x = na == 2 ? 0 : na + 1;
+        const int ux = x == 0 ? tw[j][0] : (x == 1 ? tw[j][1] : tw[j][2]);
+        src[2 * j] = 3 * lt + na;
+        cur[2 * j] = he_next(ux < 0 ? 0 : ux);
+        lab[2 * j] = (int)(x == 0 ? fn[j][0] : (x == 1 ? fn[j][1] : fn[j][2]));
+        // prev' turn: from the frontier half-edge pa, across y = prev(pa)
+        const int pa = mp ? __builtin_ctz(mp) : 0, y = pa == 0 ? 2 : pa - 1;
+        const int uy = y == 0 ? tw[j][0] : (y == 1 ? tw[j][1] : tw[j][2]);
+        src[2 * j + 1] = 3 * lt + pa;
+        cur[2 * j + 1] = he_prev(uy < 0 ? 0 : uy);
+        lab[2 * j + 1] = (int)(y == 0 ? fn[j][0] : (y == 1 ? fn[j][1] : fn[j][2]));
+        // a non-frontier edge is interior: ux, uy >= 0 whenever the turn exists
+        err |= (mn && ux < 0) || (mp && uy < 0);
+        // first candidates: most are frontier half-edges of a triangle in the
+        // tile, which ends the turn at once
+        const int cn = cur[2 * j], tn = tri_of(cn), kn = tn - base;
+        const int cp = cur[2 * j + 1], tq = tri_of(cp), kq = tq - base;
+        const bool inn = (unsigned)kn < (unsigned)cnt, inq = (unsigned)kq < (unsigned)cnt;
+        const uint32_t fbn = s_f[inn ? kn : 0], fbq = s_f[inq ? kq : 0];
+        const bool hitn = mn && inn && fbit(fbn, cn - 3 * tn);
+        const bool hitq = mp && inq && fbit(fbq, cp - 3 * tq);
+        if (hitn) {
+            s_nx[3 * lt + na] = cn;
+            // next'(h) == twin(h): the target of h is a barrier tip
+            if (cn == (na == 0 ? tw[j][0] : (na == 1 ? tw[j][1] : tw[j][2])))
+                push_tip(rc, tips, cap_tips, d, mi, h0 + na, err);
+        }
+        if (hitq) s_pv[3 * lt + pa] = cp;
+        pend |= (mn && !hitn ? 1u : 0u) << (2 * j) | (mp && !hitq ? 1u : 0u) << (2 * j + 1);
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
         const int t = base + lt, h0 = 3 * t;
-        int nx[3] = {-1, -1, -1}, pv[3] = {-1, -1, -1};
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            if (!fbit(f[j], i)) continue;
-            const int jn = i == 2 ? 0 : i + 1, jp = i == 0 ? 2 : i - 1;
-            // a non-frontier edge is interior, so tw[j][jn] / tw[j][jp] >= 0
-            nx[i] = fbit(f[j], jn) ? h0 + jn : turn<true>(twin, tflag, he_next(tw[j][jn]), fn[j][jn]);
-            pv[i] = fbit(f[j], jp) ? h0 + jp : turn<false>(twin, tflag, he_prev(tw[j][jp]), fn[j][jp]);
-            err |= nx[i] < 0 || pv[i] < 0;
-            if (tw[j][i] >= 0 && nx[i] == tw[j][i]) tipmask |= 1 << (3 * j + i);
-        }
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            s_nx[3 * lt + i] = nx[i];
-            s_pv[3 * lt + i] = pv[i];
-        }
         // A seed whose polygon is one triangle (boundary terminal edge, both
         // other edges frontier) or two (interior terminal edge, the four
         // other edges frontier) is settled here: its loop is those 3 or 4
         // half-edges.  Such polygons have no interior vertex, so no barrier
-        // tip and no repair touches them.
-        if (f[j] & kSeedBit) {
-            const int L = (int)(f[j] & 3u), a = L == 2 ? 0 : L + 1, b = L == 0 ? 2 : L - 1;
-            bool settled = false;
-            if (fbit(f[j], a) && fbit(f[j], b)) {
-                const int g = tw[j][L];
-                if (g < 0) {
-                    record_loop(d, h0, 3);
-                    settled = true;
-                } else {
-                    const int tp = g / 3, Lp = g - 3 * tp;
-                    const int ap = Lp == 2 ? 0 : Lp + 1, bp = Lp == 0 ? 2 : Lp - 1;
-                    if (fbit(fn[j][L], ap) && fbit(fn[j][L], bp)) {
-                        const int mn = tp < t ? 3 * tp + min(ap, bp) : h0 + min(a, b);
-                        record_loop(d, mn, 4);
-                        settled = true;
-                    }
-                }
-            }
-            if (!settled) openmask |= 1 << j;
-        }
+        // tip and no repair touches them.  The seed is the lower half-edge of
+        // its terminal edge, so the loop's minimum lies in this triangle and
+        // its byte is written here with the rest of the tile.
+        const int L = (int)(f[j] & 3u), a = L == 2 ? 0 : L + 1, b = L == 0 ? 2 : L - 1;
+        const bool cand = (f[j] & kSeedBit) && fbit(f[j], a) && fbit(f[j], b);
+        const int g = L == 0 ? tw[j][0] : (L == 1 ? tw[j][1] : tw[j][2]);
+        const int tp = tri_of(g < 0 ? 0 : g), Lp = g - 3 * tp;
+        const int ap = Lp == 2 ? 0 : Lp + 1, bp = Lp == 0 ? 2 : Lp - 1;
+        const int kp = tp - base;
+        const bool inp = (unsigned)kp < (unsigned)cnt;
+        const uint32_t fp = s_f[inp ? kp : 0];
+        bool quad = fbit(fp, ap) && fbit(fp, bp);
+        if (cand && g >= 0 && !inp)   // partner outside the tile (rare on ordered meshes)
+            quad = outside_fbit(T, 3 * tp + ap, Lp) && outside_fbit(T, 3 * tp + bp, Lp);
+        const uint8_t code = !cand ? (uint8_t)0
+                             : g < 0 ? loop_code(h0, 3)
+                             : !quad ? (uint8_t)0
+                             : tp == t + 1 ? (uint8_t)((kPlQuadNext << 2) | Lp)
+                                           : loop_code(h0 + min(a, b), 4);
+        openmask |= ((f[j] & kSeedBit) && !code) ? 1 << j : 0;
+        s_pl[lt] = code;   // entries past cnt are never stored
     }
-    // open seeds go to the walk list (stripe by tile, one atomic per block)
+    // One block scan places the turns still open in the LDS queue and the
+    // open seeds in the walk list (stripe by tile, one atomic per block).
     {
         __shared__ int s_scan[72];
-        __shared__ int s_base;
-        bool full = false;
-        int e = block_reserve(walk_counts, walk_cap, tile % kStripes, __popc(openmask), s_scan, &s_base, &full);
-        const int lim = (tile % kStripes + 1) * walk_cap;
+        __shared__ int s_wbase;
+        int eq, eo, tq, to;
+        block_excl_scan2(__popc(pend), __popc(openmask), eq, eo, tq, to, s_scan);
+        const int stripe = tile % kStripes;
+        if (tid == 0) s_wbase = to > 0 ? atomicAdd(&walk_counts[stripe * kStripePad], to) : 0;
+#pragma unroll
+        for (int k = 0; k < 2 * ITEMS; k++) {
+            if (!((pend >> k) & 1u)) continue;
+            if (eq < qcap) {
+                s_q[2 * eq] = cur[k];
+                s_q[2 * eq + 1] = (src[k] << 3) | ((k & 1) == 0 ? 4 : 0) | (lab[k] + 1);
+                pend &= ~(1u << k);
+            }
+            ++eq;
+        }
+        __syncthreads();
+        const int wbase = s_wbase;
+        err |= wbase + to > walk_cap;
+        int e = stripe * walk_cap + wbase + eo;
+        const int lim = (stripe + 1) * walk_cap;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             if (!((openmask >> j) & 1)) continue;
@@ -495,27 +642,45 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             }
             ++e;
         }
-        err |= full;
+        // the queued turns, one per thread: only the first lanes of the block work
+        const int nq = min(tq, qcap);
+        for (int q = tid; q < nq; q += B) {
+            const int w = s_q[2 * q + 1], sh = w >> 3;
+            const bool nxt = (w & 4) != 0;
+            const int res = run_turn(T, s_q[2 * q], (w & 3) - 1, nxt);
+            err |= res < 0;
+            if (nxt) {
+                s_nx[sh] = res;
+                if (res >= 0 && res == s_tw[sh]) push_tip(rc, tips, cap_tips, d, mi, 3 * base + sh, err);
+            } else {
+                s_pv[sh] = res;
+            }
+        }
+    }
+    // turns beyond the queue (meshes whose polygons are mostly large), in registers
+    for (int step = 0; pend; step++) {
+#pragma unroll
+        for (int k = 0; k < 2 * ITEMS; k++) {
+            if (!((pend >> k) & 1u)) continue;
+            const int r = step < kRotGuard ? turn_step(T, cur[k], lab[k], (k & 1) == 0) : -1;
+            if (r == 0) continue;
+            const int res = r > 0 ? cur[k] : -1;
+            err |= r < 0;
+            if ((k & 1) == 0) {
+                s_nx[src[k]] = res;
+                if (res >= 0 && res == s_tw[src[k]]) push_tip(rc, tips, cap_tips, d, mi, 3 * base + src[k], err);
+            } else {
+                s_pv[src[k]] = res;
+            }
+            pend &= ~(1u << k);
+        }
     }
     __syncthreads();
     if (cnt > 0) {
-        store_from_lds(d.next_o + 3 * (size_t)base, s_nx, 3 * cnt);
-        store_from_lds(d.prev_o + 3 * (size_t)base, s_pv, 3 * cnt);
-    }
-    // barrier tips (rare): one list append per wave and slot
-#pragma unroll
-    for (int k = 0; k < 3 * ITEMS; k++) {
-        const bool tip = (tipmask >> k) & 1;
-        const int slot = wave_reserve(&rc->ntips, tip);
-        if (tip) {
-            if (slot < cap_tips) {
-                tips[slot].mesh = mi;
-                tips[slot].he = 3 * (base + (k / 3) * B + tid) + k % 3;
-                atomicAdd(&d.ctr->ntips, 1);
-            } else {
-                err = true;
-            }
-        }
+        store_from_lds((gint)(d.next_o) + 3 * (size_t)base, s_nx, 3 * cnt);
+        store_from_lds((gint)(d.prev_o) + 3 * (size_t)base, s_pv, 3 * cnt);
+        store_bytes_from_lds((gu8)(d.pl) + base, s_pl, cnt);
+        store_bytes_from_lds(tflag + base, s_f, cnt);
     }
     if (err) atomicOr(&d.ctr->err, kErrCorrupt);
 }
@@ -679,7 +844,7 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
     const int total = striped_prefix(walk_counts, walk_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
     for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
-        const int32_t *nx[ITEMS];
+        gcint nx[ITEMS];
         int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], len[ITEMS], lim[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
@@ -692,10 +857,10 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
             const ListEntry e = walk[striped_index(s_pref, walk_cap, g)];
             const MeshDesc &d = descs[e.mesh];
             mesh[j] = e.mesh;
-            nx[j] = d.next_o;
+            nx[j] = (gcint)d.next_o;
             lim[j] = 3 * d.nt;
-            const int t = e.he / 3;
-            const uint32_t f = d.tflag[t];
+            const int t = tri_of(e.he);
+            const uint32_t f = ((gcu8)d.tflag)[t];
             int st = fbit(f, e.he - 3 * t) ? e.he : -1;
 #pragma unroll
             for (int i = 0; i < 3; i++)
@@ -740,8 +905,8 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
     const int total = striped_prefix(emit_counts, emit_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
     for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
-        const int32_t *nx[ITEMS];
-        int32_t *out[ITEMS];
+        gcint nx[ITEMS];
+        gint out[ITEMS];
         int mesh[ITEMS], cur[ITEMS], mn[ITEMS], pos[ITEMS], lim[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
@@ -754,8 +919,8 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
             const EmitEntry e = emit[striped_index(s_pref, emit_cap, g)];
             const MeshDesc &d = descs[e.mesh];
             mesh[j] = e.mesh;
-            nx[j] = d.next_o;
-            out[j] = d.loop_he;
+            nx[j] = (gcint)d.next_o;
+            out[j] = (gint)d.loop_he;
             cur[j] = mn[j] = e.mn;
             pos[j] = e.off;
             lim[j] = 3 * d.nt;
@@ -871,13 +1036,14 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     const int ltile = tile - d.cmp_tile0;
     const int mesh_tiles = nt > 0 ? (nt + TB - 1) / TB : 1;
     const int t0 = ltile * TB + tid * ITEMS;
-    const int32_t *__restrict__ nx = d.next_o;
+    const gcint nx = (gcint)d.next_o;
+    const gcu8 plb = (gcu8)d.pl, tfl = (gcu8)d.tflag;
 
     // 1. loop minima and lengths of this thread's ITEMS contiguous triangles
     uint8_t code[ITEMS], fl[ITEMS];
     if (ITEMS == 4 && t0 + 4 <= nt) {
-        const uint32_t w = *reinterpret_cast<const uint32_t *>(d.pl + t0);
-        const uint32_t v = *reinterpret_cast<const uint32_t *>(d.tflag + t0);
+        const uint32_t w = *reinterpret_cast<GLOBAL const uint32_t *>(plb + t0);
+        const uint32_t v = *reinterpret_cast<GLOBAL const uint32_t *>(tfl + t0);
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             code[j] = (uint8_t)(w >> (8 * (j & 3)));
@@ -886,8 +1052,8 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            code[j] = t0 + j < nt ? d.pl[t0 + j] : 0;
-            fl[j] = t0 + j < nt ? d.tflag[t0 + j] : 0;
+            code[j] = t0 + j < nt ? plb[t0 + j] : 0;
+            fl[j] = t0 + j < nt ? tfl[t0 + j] : 0;
         }
     }
     int lens[ITEMS];
@@ -898,6 +1064,7 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         lens[j] = 0;
         if (code[j]) {
             int len = code[j] >> 2;
+            if (len == kPlQuadNext) len = 4;
             if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
             if (len <= 0) {
                 bad = true;
@@ -957,7 +1124,10 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         p1[j] = -1;
         quad[j] = defer[j] = false;
         if (!code[j]) continue;
-        const int t = t0 + j, mn = 3 * t + (code[j] & 3);
+        const int t = t0 + j;
+        const uint32_t fb = (fl[j] >> 2) & 7u;
+        const bool qn = (code[j] >> 2) == kPlQuadNext;
+        const int mn = 3 * t + (qn ? __builtin_ctz(fb | 8u) : (code[j] & 3));
         const bool place = fits || (pc + q < nt && ps + off + lens[j] <= nh);
         if (!place) {
             bad = true;
@@ -969,17 +1139,22 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
                 d.seeds[pc + q] = mn;
                 d.loop_off[pc + q] = ps + off;
             }
-            const uint32_t fb = (fl[j] >> 2) & 7u;
             if (lens[j] == 3) {
                 he_out[off] = mn;
                 he_out[off + 1] = he_next(mn);
                 he_out[off + 2] = he_prev(mn);
             } else if (lens[j] == 4 && __popc(fb) == 2) {
-                const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);   // non-frontier edge
-                const int bb = 3 * t + (sx == 0 ? 2 : sx - 1);
-                p1[j] = nx[bb];
+                if (qn) {   // the second triangle is t + 1: next'(b) leaves its terminal edge
+                    const int Lp = code[j] & 3;
+                    p1[j] = 3 * (t + 1) + (Lp == 2 ? 0 : Lp + 1);
+                } else {
+                    const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);   // non-frontier edge
+                    p1[j] = nx[3 * t + (sx == 0 ? 2 : sx - 1)];
+                }
                 pos[j] = off;
                 quad[j] = true;
+            } else if (qn) {
+                bad = true;
             } else if (lens[j] > 0) {
                 pos[j] = ps + off;
                 defer[j] = true;
@@ -1012,7 +1187,7 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     for (int j = 0; j < ITEMS; j++) {
         if (!quad[j]) continue;
         const uint32_t fb = (fl[j] >> 2) & 7u;
-        const int t = t0 + j, mn = 3 * t + (code[j] & 3);
+        const int t = t0 + j, mn = 3 * t + ((code[j] >> 2) == kPlQuadNext ? __builtin_ctz(fb) : (code[j] & 3));
         const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
         const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
         const int o = pos[j];
@@ -1033,11 +1208,12 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     if (fits) {
         __syncthreads();
         // contiguous stores of the tile's part of seeds, loop_off, loop_he
+        const gint seeds = (gint)d.seeds, loff = (gint)d.loop_off, lhe = (gint)d.loop_he;
         for (int k = tid; k < tcnt; k += B) {
-            d.seeds[pc + k] = s_seed[k];
-            d.loop_off[pc + k] = ps + s_off[k];
+            seeds[pc + k] = s_seed[k];
+            loff[pc + k] = ps + s_off[k];
         }
-        for (int k = tid; k < tsum; k += B) d.loop_he[ps + k] = s_he[k];
+        for (int k = tid; k < tsum; k += B) lhe[ps + k] = s_he[k];
     }
     if (bad) atomicOr(&d.ctr->err, kErrCorrupt);
 }
@@ -1080,14 +1256,9 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
                     sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh);
     H(K_LABEL, 1);
 
-    H(K_FRONTIER, 0);
-    GP_LAUNCH_ITEMS(k_frontier, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                    sizeof(int) * 3 * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh);
-    H(K_FRONTIER, 1);
-
     H(K_RELINK, 0);
     GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                    sizeof(int) * 6 * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
+                    (sizeof(int) * 9 + 2 + 4) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
                     rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap);
     H(K_RELINK, 1);
 

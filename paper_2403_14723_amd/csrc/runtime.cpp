@@ -416,6 +416,61 @@ const char *gpolylla_strerror(int code) {
     }
 }
 
+namespace {
+
+// Per-kernel launch shapes, "label=256x4,relink=256x2,compact=512x4,
+// persist=1024x256" (any subset, any order; persist is blocks x threads of the
+// list-driven kernels).  Every entry is checked; on any error *cfg is left as
+// it was.  Tiles are then clamped to what each kernel's LDS staging allows.
+int parse_launch_spec(const char *spec, gp::LaunchCfg *cfg) {
+    gp::LaunchCfg g = *cfg;
+    const std::string sp(spec);
+    size_t p0 = 0;
+    while (p0 < sp.size()) {
+        size_t p1 = sp.find(',', p0);
+        if (p1 == std::string::npos) p1 = sp.size();
+        const std::string item = sp.substr(p0, p1 - p0);
+        p0 = p1 + 1;
+        const size_t eq = item.find('='), x = item.find('x', eq == std::string::npos ? 0 : eq);
+        if (eq == std::string::npos || x == std::string::npos) return GP_EINVAL;
+        const std::string k = item.substr(0, eq), sb = item.substr(eq + 1, x - eq - 1), si = item.substr(x + 1);
+        if (sb.empty() || si.empty() || sb.size() > 6 || si.size() > 6 ||
+            sb.find_first_not_of("0123456789") != std::string::npos ||
+            si.find_first_not_of("0123456789") != std::string::npos)
+            return GP_EINVAL;
+        const int b = std::atoi(sb.c_str()), it = std::atoi(si.c_str());
+        const bool ok_b = b >= 64 && b <= 1024 && b % 64 == 0;
+        const bool ok_i = it == 1 || it == 2 || it == 4 || it == 8;
+        if (k == "persist") {
+            if (!ok_b || it < 1 || it > 65536) return GP_EINVAL;
+            g.block_persistent = b;
+            g.persistent_blocks = it;
+        } else if (!ok_b || !ok_i) {
+            return GP_EINVAL;
+        } else if (k == "label") {
+            g.block_label = b;
+            g.items_label = it;
+        } else if (k == "relink") {
+            g.block_relink = b;
+            g.items_relink = it;
+        } else if (k == "compact") {
+            g.block_compact = b;
+            g.items_compact = it;
+        } else {
+            return GP_EINVAL;
+        }
+    }
+    // LDS per tile: k_label stages 12 bytes per triangle (tile <= 4096),
+    // k_relink 42 bytes (tile <= 1024), k_compact 20 bytes (tile <= 2048)
+    while ((int64_t)g.block_label * g.items_label > 4096 && g.items_label > 1) g.items_label /= 2;
+    while ((int64_t)g.block_relink * g.items_relink > 1024 && g.items_relink > 1) g.items_relink /= 2;
+    while ((int64_t)g.block_compact * g.items_compact > 2048 && g.items_compact > 1) g.items_compact /= 2;
+    *cfg = g;
+    return GP_OK;
+}
+
+}  // namespace
+
 int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
     if (!out) return GP_EINVAL;
     *out = nullptr;
@@ -447,48 +502,9 @@ int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
             c->cfg.items_label = c->cfg.items_relink = c->cfg.items_compact = opts->items;
         }
     }
-    {
-        // optional per-kernel launch shapes, "label=256x4,relink=256x4,compact=256x4,persist=1024x256"
-        // (the autotuner's hook); malformed entries are ignored
-        gp::LaunchCfg &g = c->cfg;
-        if (const char *env = std::getenv("GPOLYLLA_CFG")) {
-            std::string spec(env);
-            size_t p0 = 0;
-            while (p0 < spec.size()) {
-                size_t p1 = spec.find(',', p0);
-                if (p1 == std::string::npos) p1 = spec.size();
-                std::string item = spec.substr(p0, p1 - p0);
-                p0 = p1 + 1;
-                size_t eq = item.find('='), x = item.find('x');
-                if (eq == std::string::npos || x == std::string::npos || x < eq) continue;
-                int b = std::atoi(item.substr(eq + 1, x - eq - 1).c_str());
-                int it = std::atoi(item.substr(x + 1).c_str());
-                std::string k = item.substr(0, eq);
-                bool ok_b = b >= 64 && b <= 1024 && b % 64 == 0;
-                bool ok_i = it == 1 || it == 2 || it == 4 || it == 8;
-                if (k == "persist") {
-                    if (b >= 64 && b <= 1024 && b % 64 == 0 && it >= 1 && it <= 65536) {
-                        g.block_persistent = b;
-                        g.persistent_blocks = it;
-                    }
-                    continue;
-                }
-                if (!ok_b || !ok_i) continue;
-                if (k == "label") { g.block_label = b; g.items_label = it; }
-                else if (k == "relink") { g.block_relink = b; g.items_relink = it; }
-                else if (k == "compact") { g.block_compact = b; g.items_compact = it; }
-            }
-        }
-    }
-    {
-        // LDS per tile: k_label and k_frontier stage 12 bytes per triangle
-        // (tile <= 4096), k_relink 24 bytes (tile <= 1024), k_compact 20
-        // bytes (tile <= 2048)
-        gp::LaunchCfg &g = c->cfg;
-        while ((int64_t)g.block_label * g.items_label > 4096 && g.items_label > 1) g.items_label /= 2;
-        while ((int64_t)g.block_relink * g.items_relink > 1024 && g.items_relink > 1) g.items_relink /= 2;
-        while ((int64_t)g.block_compact * g.items_compact > 2048 && g.items_compact > 1) g.items_compact /= 2;
-    }
+    (void)parse_launch_spec("", &c->cfg);   // clamps the tiles of opts->block x opts->items
+    if (const char *env = std::getenv("GPOLYLLA_CFG"))
+        (void)parse_launch_spec(env, &c->cfg);   // launch shapes from the environment; ignored if malformed
     if (opts && opts->stream) {
         c->stream = static_cast<hipStream_t>(opts->stream);
     } else {
@@ -558,6 +574,26 @@ void gpolylla_ctx_kernel_reset(gp_ctx *c) {
         c->kms[k] = 0;
         c->kcount[k] = 0;
     }
+}
+
+int gpolylla_ctx_set_launch(gp_ctx *c, const char *spec) {
+    if (!c || !spec) return GP_EINVAL;
+    return parse_launch_spec(spec, &c->cfg);
+}
+
+int gpolylla_ctx_get_launch(const gp_ctx *c, char *buf, int32_t cap) {
+    if (!c) return GP_EINVAL;
+    const gp::LaunchCfg &g = c->cfg;
+    char tmp[160];
+    const int n = std::snprintf(tmp, sizeof tmp, "label=%dx%d,relink=%dx%d,compact=%dx%d,persist=%dx%d",
+                                g.block_label, g.items_label, g.block_relink, g.items_relink, g.block_compact,
+                                g.items_compact, g.block_persistent, g.persistent_blocks);
+    if (buf && cap > 0) {
+        const int m = n < cap - 1 ? n : cap - 1;
+        std::memcpy(buf, tmp, (size_t)m);
+        buf[m] = 0;
+    }
+    return n + 1;
 }
 
 // ---------------------------------------------------------------------------

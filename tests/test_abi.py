@@ -54,3 +54,5 @@ def test_argument_errors_without_gpu(lib):
     assert lib.gpolylla_mesh(None, None, 0, None) == gp.GP_EINVAL
     assert lib.gpolylla_build_halfedges(None, None, 0, None, 0, 0, None) == gp.GP_EINVAL
     assert lib.gpolylla_result_info(None, None) == gp.GP_EINVAL
+    assert lib.gpolylla_ctx_set_launch(None, b"label=256x4") == gp.GP_EINVAL
+    assert lib.gpolylla_ctx_get_launch(None, None, 0) == gp.GP_EINVAL

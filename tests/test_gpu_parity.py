@@ -248,3 +248,30 @@ def test_graph_replays_match_eager(ctx):
         ctx.sync()
     for h in hs:
         h.free()
+
+
+def test_launch_spec_roundtrip_and_errors():
+    with gp.Context(0) as c:
+        c.set_launch("label=512x2,relink=128x4,compact=256x8,persist=256x512")
+        assert c.launch() == "label=512x2,relink=128x4,compact=256x8,persist=256x512"
+        before = c.launch()
+        for bad in ("label=100x2", "relink=256x3", "nope=256x2", "label=256", "label=x2", "label=256x2,,x",
+                    "compact=2048x1", "persist=256x0", "label=256x2;relink=256x2"):
+            with pytest.raises(gp.GPolyllaError) as e:
+                c.set_launch(bad)
+            assert e.value.code == gp.GP_EINVAL, bad
+            assert c.launch() == before, bad
+        # tiles beyond the LDS staging are clamped by halving the items
+        c.set_launch("relink=1024x8,label=1024x8,compact=1024x8")
+        assert c.launch().startswith("label=1024x4,relink=1024x1,compact=1024x2")
+
+
+@pytest.mark.parametrize("spec", ["label=64x1,relink=64x1,compact=64x1,persist=64x1",
+                                  "label=1024x4,relink=128x8,compact=128x8,persist=1024x4096"])
+def test_launch_specs_do_not_change_results(spec):
+    m = W.random_delaunay(20000, 41)
+    o = oracle.polylla(m.xy, m.tri)
+    with gp.Context(0) as c:
+        c.set_launch(spec)
+        g = run_gpu(c, m.xy, m.tri, f"{m.name} {spec}")
+    assert_parity(g, o, spec)
