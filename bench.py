@@ -12,6 +12,7 @@ host<->device copies are timed separately and reported beside the headline.
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -49,6 +50,21 @@ def kernel_bytes(name, nt, nv, npoly, nloop):
         "k_relink": 12 * nt + nt + 24 * nt + 2 * nt,          # twin, tflag -> next, prev, tflag, pl
         "k_compact": 2 * nt + 8 * npoly + 4 * nloop,          # pl, tflag -> seeds, loop_off, loop_he
     }.get(name)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated), when the summary was taken on the
+    kernel sources as they are now; else None."""
+    from paper_2403_14723_amd import prof
+    here = os.path.dirname(os.path.abspath(__file__))
+    sha = prof.sources_sha256()
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+        with open(path) as f:
+            rec = prof.traffic_line(f.read())
+        if rec and rec.get("kernel") == kernel and rec.get("sources_sha256") == sha:
+            return rec["fetch_bytes"] + rec["write_bytes"], os.path.basename(path)
+    return None, None
 
 
 def cpu_baseline(mesh):
@@ -211,7 +227,10 @@ def main():
     # torch's copies and events are ordered with the library's kernels
     stream = torch.cuda.Stream(dev)
     torch.cuda.set_stream(stream)
-    ctx = gp.Context(0, stream=stream.cuda_stream, profile=True)
+    # the timed steps replay the captured chain on a plain context; the
+    # per-kernel times come from a separate pass on a profiling context
+    # (its events between kernels would otherwise sit in the timed region)
+    ctx = gp.Context(0, stream=stream.cuda_stream)
 
     # host -> device copy of the inputs from pinned memory (reported apart)
     xy_h = torch.from_numpy(mesh.xy).pin_memory()
@@ -228,11 +247,11 @@ def main():
     build_ms = e1.elapsed_time(e2)
     log(f"[bench] H2D {h2d_ms:.2f} ms, build {build_ms:.2f} ms")
 
+    step_flags = gp.GP_ASYNC | gp.GP_GRAPH
     for _ in range(args.warmup):
-        r = ctx.mesh(h, gp.GP_ASYNC)
+        r = ctx.mesh(h, step_flags)
         r.free()
     ctx.sync()
-    ctx.kernel_reset()
     log(f"[bench] warmup done; timing {args.steps} steps")
 
     torch.cuda.synchronize()
@@ -241,15 +260,28 @@ def main():
     w0 = time.perf_counter()
     t_start.record(stream)
     for _ in range(args.steps):
-        r = ctx.mesh(h, gp.GP_ASYNC)
+        r = ctx.mesh(h, step_flags)
         r.free()
     t_end.record(stream)
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - w0
     ctx.sync()
     ms_per_step = t_start.elapsed_time(t_end) / args.steps
-    kms = ctx.kernel_ms()
     log(f"[bench] {ms_per_step:.3f} ms/step (wall {wall_s * 1e3 / args.steps:.3f} ms/step)")
+
+    # per-kernel device times: HIP events around every kernel, same stream
+    pctx = gp.Context(0, stream=stream.cuda_stream, profile=True)
+    ph = pctx.build_halfedges(xy_d, tri_d)
+    for _ in range(2):
+        pctx.mesh(ph, gp.GP_ASYNC).free()
+    pctx.sync()
+    pctx.kernel_reset()
+    for _ in range(max(3, args.steps // 2)):
+        pctx.mesh(ph, gp.GP_ASYNC).free()
+    pctx.sync()
+    kms = pctx.kernel_ms()
+    ph.free()
+    pctx.close()
 
     # one more run for counts and the device->host copy time of all outputs
     # into pinned host buffers (reported apart from the headline)
@@ -287,6 +319,7 @@ def main():
     dom_bytes = kernel_bytes(dom, nt, nv, P, Fh)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     value = nt / (ms_per_step * 1e-3) / 1e6
+    traffic, traffic_src = measured_traffic(dom.split("<")[0])
 
     batched = served = None
     if not args.no_forms:
@@ -320,7 +353,7 @@ def main():
                    "ties": info["nties"], "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "alg_bytes_per_launch": dom_bytes},
+                     "traffic": traffic, "traffic_source": traffic_src, "alg_bytes_per_launch": dom_bytes},
         "whole_path": {"alg_bytes": b_alg, "alg_GBs": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
                        "frac": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kernels,

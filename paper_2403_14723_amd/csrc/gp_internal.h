@@ -103,7 +103,7 @@ struct RunBuffers {
     ListEntry *tips;         // capacity cap_tips
     ListEntry *fixes;        // capacity cap_fix
     int32_t cap_tips, cap_fix;
-    uint64_t *status;        // compaction tile status, cmp_tiles entries
+    uint64_t *status;        // per compaction tile: (loops << 32 | half-edges), then its exclusive prefix
     MeshCounters *ctrs;      // device, nmesh entries
     ListEntry *walk;         // striped: seeds left open by k_relink and repair seeds
     int32_t *walk_counts;    // kStripes counters, kStripePad ints apart
@@ -113,7 +113,7 @@ struct RunBuffers {
     int32_t emit_cap;        // per stripe
 };
 
-enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_COMPACT, K_EMIT, K_COUNT };
+enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.

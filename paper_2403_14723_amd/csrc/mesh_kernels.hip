@@ -22,9 +22,10 @@
 //               minimum and length at the minimum's triangle (Section 6.6,
 //               Algorithm 14).  Polygons of one or two triangles are settled
 //               by k_relink itself.
-//   k_compact   scan of loop minima and lengths (decoupled look-back) that
-//               writes seeds, loop offsets and the loops of up to four
-//               half-edges (Section 6.7)
+//   k_tile_scan exclusive scan of the per-tile loop totals that k_relink and
+//               k_walk accumulate (Section 6.7)
+//   k_compact   writes seeds, loop offsets and the loops of up to four
+//               half-edges of every tile from its prefix (Section 6.7)
 //   k_emit      writes the longer loops at the offsets k_compact reserved
 //
 // Label byte per triangle (tflag):
@@ -36,8 +37,8 @@
 
 namespace gp {
 
-const char *const kKernelNames[K_COUNT] = {"k_init", "k_label",   "k_relink", "k_repair", "k_fixup",
-                                           "k_walk", "k_compact", "k_emit"};
+const char *const kKernelNames[K_COUNT] = {"k_init", "k_label",     "k_relink",  "k_repair", "k_fixup",
+                                           "k_walk", "k_tile_scan", "k_compact", "k_emit"};
 
 constexpr uint32_t kSeedBit = 1u << 5;
 
@@ -373,9 +374,20 @@ __device__ __forceinline__ uint8_t loop_code(int mn, int len) {
 }
 constexpr int kPlQuadNext = 1;
 
-// Records loop (minimum mn, length len) in the byte of the minimum's triangle.
-__device__ __forceinline__ void record_loop(const MeshDesc &d, int mn, int len) {
-    ((gu8)d.pl)[tri_of(mn)] = loop_code(mn, len);
+// Records a walked loop (minimum mn, length len) once: the walker that sets
+// the byte of the minimum's triangle adds the loop to the totals of that
+// triangle's compaction tile.  After a repair several seeds of one polygon
+// walk the same loop; only the first counts it.
+__device__ __forceinline__ void claim_loop(const MeshDesc &d, int mn, int len, uint64_t *agg, int cmp_tb) {
+    const int tm = tri_of(mn);
+    const uint32_t code = loop_code(mn, len);
+    uint32_t *w = reinterpret_cast<uint32_t *>(d.pl) + (tm >> 2);
+    const int sh = 8 * (tm & 3);
+    // every walker of this loop writes the same code, so OR-ing it in is
+    // safe; the one that found the byte empty counts the loop
+    if ((atomicOr(w, code << sh) >> sh) & 0xffu) return;
+    atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + tm / cmp_tb),
+              (1ull << 32) | (unsigned long long)(uint32_t)len);
 }
 
 // Copies n bytes from LDS src to global dst; both 4-byte aligned.
@@ -460,7 +472,8 @@ __device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc)
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
                                                   RunCounters *rc, ListEntry *tips, int cap_tips,
-                                                  ListEntry *walk, int32_t *walk_counts, int walk_cap) {
+                                                  ListEntry *walk, int32_t *walk_counts, int walk_cap,
+                                                  uint64_t *agg, int cmp_tb) {
     extern __shared__ int4 lds_raw[];
     int *lds = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x, TB = B * ITEMS;
@@ -529,6 +542,8 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     const TileLabels T = {twin, tflag, s_tw, s_f, base, cnt};
     bool err = false;
     int openmask = 0;   // bit j: item j holds a seed whose loop k_walk must walk
+    int scnt = 0, slen = 0;   // loops settled here: count, half-edges
+    uint8_t codes[ITEMS];
     uint32_t pend = 0;  // bit 2j (2j+1): the next' (prev') turn of item j goes on
     int cur[2 * ITEMS], lab[2 * ITEMS], src[2 * ITEMS];   // turn state; src: the
                                                           // local index of the half-edge
@@ -607,16 +622,42 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
                                            : loop_code(h0 + min(a, b), 4);
         openmask |= ((f[j] & kSeedBit) && !code) ? 1 << j : 0;
         s_pl[lt] = code;   // entries past cnt are never stored
+        codes[j] = code;
+        scnt += code ? 1 : 0;
+        slen += !code ? 0 : (code >> 2) == kPlQuadNext ? 4 : (code >> 2);
     }
     // One block scan places the turns still open in the LDS queue and the
-    // open seeds in the walk list (stripe by tile, one atomic per block).
+    // open seeds in the walk list (stripe by tile, one atomic per block), and
+    // totals the loops settled here for their compaction tile.  Each count
+    // fits in 16 bits (at most 2 per triangle, lengths at most 4 per
+    // triangle, tiles of at most 1024 triangles), so two ride in one int.
     {
         __shared__ int s_scan[72];
         __shared__ int s_wbase;
-        int eq, eo, tq, to;
-        block_excl_scan2(__popc(pend), __popc(openmask), eq, eo, tq, to, s_scan);
+        int ea, eb, ta, tb;
+        block_excl_scan2((__popc(pend) << 16) | __popc(openmask), (scnt << 16) | slen, ea, eb, ta, tb, s_scan);
+        int eq = ea >> 16;
+        const int eo = ea & 0xffff, tq = ta >> 16, to = ta & 0xffff;
         const int stripe = tile % kStripes;
-        if (tid == 0) s_wbase = to > 0 ? atomicAdd(&walk_counts[stripe * kStripePad], to) : 0;
+        // the block's triangles lie in one compaction tile unless that tile is
+        // smaller than this one or not aligned with it
+        const bool one = base / cmp_tb == (base + cnt - 1) / cmp_tb;
+        if (tid == 0) {
+            s_wbase = to > 0 ? atomicAdd(&walk_counts[stripe * kStripePad], to) : 0;
+            if (one && tb != 0)
+                atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + base / cmp_tb),
+                          ((unsigned long long)(uint32_t)(tb >> 16) << 32) | (unsigned long long)(tb & 0xffff));
+        }
+        if (!one) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if (!codes[j]) continue;
+                const int t = base + j * B + tid;
+                const int len = (codes[j] >> 2) == kPlQuadNext ? 4 : (codes[j] >> 2);
+                atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + t / cmp_tb),
+                          (1ull << 32) | (unsigned long long)len);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 2 * ITEMS; k++) {
             if (!((pend >> k) & 1u)) continue;
@@ -839,7 +880,8 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
 // sit in registers.
 template <int ITEMS>
 __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
-                                              const int32_t *walk_counts, int walk_cap) {
+                                              const int32_t *walk_counts, int walk_cap, uint64_t *agg,
+                                              int cmp_tb) {
     __shared__ int s_pref[kStripes + 1];
     const int total = striped_prefix(walk_counts, walk_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
@@ -887,7 +929,7 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                     continue;
                 }
                 if (cur[j] == start[j]) {
-                    record_loop(descs[mesh[j]], mn[j], len[j]);
+                    claim_loop(descs[mesh[j]], mn[j], len[j], agg, cmp_tb);
                     start[j] = -1;
                     continue;
                 }
@@ -953,69 +995,84 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
 }
 
 // ---------------------------------------------------------------------------
-// k_compact: decoupled look-back scan of (loop count, loop length) per mesh;
-// each tile assembles its seeds, offsets and loops in LDS and writes them out
-// contiguously
+// k_tile_scan: exclusive scan of the compaction tiles' loop totals
+//
+// k_relink (settled loops) and k_walk (walked loops) add every loop, once, to
+// the total of the compaction tile holding its minimum: (loops << 32 |
+// half-edges).  One block per mesh turns the totals into exclusive prefixes
+// in place and records the mesh's polygon and loop half-edge counts, so each
+// k_compact tile starts with its output offsets known.
 // ---------------------------------------------------------------------------
 
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagInc = 2ull << 62;
-constexpr int kSpinGuard = 1 << 26;
-
-__device__ __forceinline__ uint64_t pack_status(uint64_t flag, int cnt, int sum) {
-    return flag | (((uint64_t)(uint32_t)cnt << 32) & 0x3fffffff00000000ull) | (uint32_t)sum;
+__global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__ descs, uint64_t *status,
+                                                     int cmp_tb) {
+    __shared__ int s_scan[72];
+    const MeshDesc &d = descs[blockIdx.x];
+    const int ntiles = d.nt > 0 ? (d.nt + cmp_tb - 1) / cmp_tb : 1;
+    uint64_t *st = status + d.cmp_tile0;
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int per = (ntiles + B - 1) / B;
+    const int k0 = min(tid * per, ntiles), k1 = min(k0 + per, ntiles);
+    // eight loads in flight per thread (indices clamped, values masked)
+    int c = 0, h = 0;
+    for (int k = k0; k < k1; k += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = st[min(k + u, k1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const uint64_t x = k + u < k1 ? v[u] : 0ull;
+            c += (int)(x >> 32);
+            h += (int)(uint32_t)x;
+        }
+    }
+    int ec, eh, tc, th;
+    block_excl_scan2(c, h, ec, eh, tc, th, s_scan);
+    for (int k = k0; k < k1; k += 8) {
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = st[min(k + u, k1 - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            if (k + u >= k1) break;
+            st[k + u] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
+            ec += (int)(v[u] >> 32);
+            eh += (int)(uint32_t)v[u];
+        }
+    }
+    if (tid == 0) {
+        const bool ok = tc >= 0 && th >= 0 && tc <= d.nt && th <= 3 * d.nt;
+        d.ctr->npoly = ok ? tc : 0;
+        d.ctr->nloop = ok ? th : 0;
+        if (ok)
+            d.loop_off[tc] = th;
+        else
+            atomicOr(&d.ctr->err, kErrCorrupt);
+    }
 }
+
+// ---------------------------------------------------------------------------
+// k_compact: seeds, loop offsets and loops of every tile, from the tile's
+// prefix; each tile assembles its part in LDS and writes it contiguously
+// ---------------------------------------------------------------------------
 
 // Length of the loop starting at mn (when it did not fit in the byte).
 __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
+    const gcint nx = (gcint)d.next_o;
     const int nh = 3 * d.nt;
     int cur = mn, len = 0;
     do {
         ++len;
-        cur = d.next_o[cur];
+        cur = nx[cur];
         if (cur < 0 || len > nh) return -1;
     } while (cur != mn);
     return len;
 }
 
-// Decoupled look-back by one wave: lane k inspects tile (end - k); tiles
-// before the mesh's first tile count as an inclusive zero.  Returns the
-// exclusive prefix (count, sum) of `tile` within its mesh.
-__device__ __forceinline__ void wave_lookback(uint64_t *status, int tile, int first, int &pc, int &ps,
-                                              bool &bad) {
-    const int lane = __lane_id();
-    pc = 0;
-    ps = 0;
-    int end = tile - 1, spins = 0;
-    while (true) {
-        const int idx = end - lane;
-        uint64_t st = idx < first ? kFlagInc
-                                  : __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (__ballot((st >> 62) == 0ull) != 0ull) {
-            if (++spins > kSpinGuard) {
-                bad = true;
-                st = kFlagInc;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            if ((st >> 62) == 0ull)
-                st = __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const unsigned long long inc = __ballot((st >> 62) == 2ull);
-        const int stop = inc ? __ffsll((long long)inc) - 1 : kWave - 1;
-        const int c = lane <= stop ? (int)((st >> 32) & 0x3fffffffull) : 0;
-        const int v = lane <= stop ? (int)(uint32_t)st : 0;
-        pc += wave_sum(c);
-        ps += wave_sum(v);
-        if (inc) break;
-        end -= kWave;
-    }
-}
-
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
-                                                  RunCounters *rc, uint64_t *status, EmitEntry *emit,
-                                                  int32_t *emit_counts, int emit_cap) {
+                                                  const uint64_t *status, EmitEntry *emit, int32_t *emit_counts,
+                                                  int emit_cap) {
     // LDS: loop half-edges (3 per triangle of the tile), seeds and local
     // offsets (one per triangle)
     extern __shared__ int4 lds_raw[];
@@ -1024,12 +1081,9 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     int *s_he = reinterpret_cast<int *>(lds_raw);
     int *s_seed = s_he + 3 * TB;
     int *s_off = s_seed + TB;
-    __shared__ int s_tile;
     __shared__ int s_scan[72];
-    __shared__ int s_prefix[2];
-    if (tid == 0) s_tile = atomicAdd(&rc->tile_ctr, 1);
-    __syncthreads();
-    const int tile = s_tile;
+    __shared__ int s_ebase;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<2>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
     const int nt = d.nt, nh = 3 * nt;
@@ -1038,8 +1092,11 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     const int t0 = ltile * TB + tid * ITEMS;
     const gcint nx = (gcint)d.next_o;
     const gcu8 plb = (gcu8)d.pl, tfl = (gcu8)d.tflag;
+    const uint64_t pre = status[tile];
+    const int pc = (int)(pre >> 32), ps = (int)(uint32_t)pre;
 
-    // 1. loop minima and lengths of this thread's ITEMS contiguous triangles
+    // 1. loop minima and lengths of this thread's ITEMS contiguous triangles;
+    //    which loops k_emit writes (longer than a quad)
     uint8_t code[ITEMS], fl[ITEMS];
     if (ITEMS == 4 && t0 + 4 <= nt) {
         const uint32_t w = *reinterpret_cast<GLOBAL const uint32_t *>(plb + t0);
@@ -1057,57 +1114,40 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         }
     }
     int lens[ITEMS];
-    int cnt = 0, sum = 0;
+    bool defer[ITEMS];
+    int cnt = 0, sum = 0, nd = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         lens[j] = 0;
-        if (code[j]) {
-            int len = code[j] >> 2;
-            if (len == kPlQuadNext) len = 4;
-            if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
-            if (len <= 0) {
-                bad = true;
-                len = 0;
-            }
-            lens[j] = len;
-            cnt += 1;
-            sum += len;
+        defer[j] = false;
+        if (!code[j]) continue;
+        int len = code[j] >> 2;
+        if (len == kPlQuadNext) len = 4;
+        if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
+        if (len <= 0) {
+            bad = true;
+            len = 0;
         }
+        lens[j] = len;
+        // loops of three and two-triangle loops of four are written here
+        defer[j] = len > 0 && len != 3 && !(len == 4 && __popc((fl[j] >> 2) & 7u) == 2);
+        cnt += 1;
+        sum += len;
+        nd += defer[j];
     }
-    // 2. block scan (tile-local offsets)
-    int ecnt, esum, tcnt, tsum;
-    block_excl_scan2(cnt, sum, ecnt, esum, tcnt, tsum, s_scan);
-    // 3. look-back over the tiles of the same mesh (first wave)
-    if (tid < kWave) {
-        int pc = 0, ps = 0;
-        if (ltile == 0) {
-            if (tid == 0)
-                __hip_atomic_store(&status[tile], pack_status(kFlagInc, tcnt, tsum), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (tid == 0)
-                __hip_atomic_store(&status[tile], pack_status(kFlagAgg, tcnt, tsum), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            wave_lookback(status, tile, d.cmp_tile0, pc, ps, bad);
-            if (tid == 0)
-                __hip_atomic_store(&status[tile], pack_status(kFlagInc, pc + tcnt, ps + tsum), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (tid == 0) {
-            s_prefix[0] = pc;
-            s_prefix[1] = ps;
-            if (ltile == mesh_tiles - 1) {
-                d.ctr->npoly = pc + tcnt;
-                d.ctr->nloop = ps + tsum;
-                d.loop_off[pc + tcnt] = ps + tsum;
-            }
-        }
+    // 2. block scan: tile-local loop index and offset, emit-list slot
+    int ecn, esum, tcn, tsum;
+    block_excl_scan2(cnt | (nd << 16), sum, ecn, esum, tcn, tsum, s_scan);
+    const int tcnt = tcn & 0xffff, tnd = tcn >> 16;
+    const int stripe = tile % kStripes;
+    if (tid == 0) {
+        s_ebase = tnd > 0 ? atomicAdd(&emit_counts[stripe * kStripePad], tnd) : 0;
+        // the tiles' prefixes must add up to the mesh totals
+        if (ltile == mesh_tiles - 1 && (pc + tcnt != d.ctr->npoly || ps + tsum != d.ctr->nloop)) bad = true;
     }
-    __syncthreads();
-    const int pc = s_prefix[0], ps = s_prefix[1];
     const bool fits = tsum <= 3 * TB && pc + tcnt <= nt && ps + tsum <= nh;
-    // 4. seeds, local offsets and loops; into LDS, or straight to global
+    // 3. seeds, local offsets and loops; into LDS, or straight to global
     //    memory for a tile whose loops do not fit
     int *he_out = fits ? s_he : d.loop_he + ps;
     // A loop of 3 is one triangle: (mn, next, prev).  A loop of 4 is two
@@ -1115,14 +1155,13 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     // and crosses to the other triangle at b, whose two frontier half-edges
     // follow as p1 = next'(b), next(p1).  Longer loops get their offset here
     // and are written by k_emit.
-    int q = ecnt, off = esum;
-    int pos[ITEMS], p1[ITEMS];
-    bool quad[ITEMS], defer[ITEMS];
+    int q = ecn & 0xffff, off = esum, e = (ecn >> 16);
+    __syncthreads();
+    e += stripe * emit_cap + s_ebase;
+    const int elim = (stripe + 1) * emit_cap;
+    bad |= s_ebase + tnd > emit_cap;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        pos[j] = 0;
-        p1[j] = -1;
-        quad[j] = defer[j] = false;
         if (!code[j]) continue;
         const int t = t0 + j;
         const uint32_t fb = (fl[j] >> 2) & 7u;
@@ -1143,67 +1182,42 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
                 he_out[off] = mn;
                 he_out[off + 1] = he_next(mn);
                 he_out[off + 2] = he_prev(mn);
-            } else if (lens[j] == 4 && __popc(fb) == 2) {
+            } else if (!defer[j] && lens[j] == 4) {
+                // non-frontier edge sx; a = next(sx), b = prev(sx); the loop
+                // crosses sx's twin into the other triangle
+                const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
+                const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
+                int p1;
                 if (qn) {   // the second triangle is t + 1: next'(b) leaves its terminal edge
                     const int Lp = code[j] & 3;
-                    p1[j] = 3 * (t + 1) + (Lp == 2 ? 0 : Lp + 1);
+                    p1 = 3 * (t + 1) + (Lp == 2 ? 0 : Lp + 1);
                 } else {
-                    const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);   // non-frontier edge
-                    p1[j] = nx[3 * t + (sx == 0 ? 2 : sx - 1)];
+                    p1 = nx[bb];
                 }
-                pos[j] = off;
-                quad[j] = true;
-            } else if (qn) {
-                bad = true;
-            } else if (lens[j] > 0) {
-                pos[j] = ps + off;
-                defer[j] = true;
+                if (p1 < 0 || (mn != aa && mn != bb)) {
+                    bad = true;
+                } else if (mn == aa) {
+                    he_out[off] = aa;
+                    he_out[off + 1] = bb;
+                    he_out[off + 2] = p1;
+                    he_out[off + 3] = he_next(p1);
+                } else {
+                    he_out[off] = bb;
+                    he_out[off + 1] = p1;
+                    he_out[off + 2] = he_next(p1);
+                    he_out[off + 3] = aa;
+                }
+            } else if (defer[j]) {
+                if (e < elim) {
+                    emit[e].mesh = mi;
+                    emit[e].mn = mn;
+                    emit[e].off = ps + off;
+                }
+                ++e;
             }
         }
         ++q;
         off += lens[j];
-    }
-    {   // longer loops go to the emit list (stripe by tile, one atomic per block)
-        __shared__ int s_base;
-        int nd = 0;
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) nd += defer[j];
-        bool full = false;
-        int e = block_reserve(emit_counts, emit_cap, tile % kStripes, nd, s_scan, &s_base, &full);
-        const int lim = (tile % kStripes + 1) * emit_cap;
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            if (!defer[j]) continue;
-            if (e < lim) {
-                emit[e].mesh = mi;
-                emit[e].mn = 3 * (t0 + j) + (code[j] & 3);
-                emit[e].off = pos[j];
-            }
-            ++e;
-        }
-        bad |= full;
-    }
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        if (!quad[j]) continue;
-        const uint32_t fb = (fl[j] >> 2) & 7u;
-        const int t = t0 + j, mn = 3 * t + ((code[j] >> 2) == kPlQuadNext ? __builtin_ctz(fb) : (code[j] & 3));
-        const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
-        const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
-        const int o = pos[j];
-        if (p1[j] < 0 || (mn != aa && mn != bb)) {
-            bad = true;
-        } else if (mn == aa) {
-            he_out[o] = aa;
-            he_out[o + 1] = bb;
-            he_out[o + 2] = p1[j];
-            he_out[o + 3] = he_next(p1[j]);
-        } else {
-            he_out[o] = bb;
-            he_out[o + 1] = p1[j];
-            he_out[o + 2] = he_next(p1[j]);
-            he_out[o + 3] = aa;
-        }
     }
     if (fits) {
         __syncthreads();
@@ -1240,6 +1254,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     };
     if (rb.nmesh <= 0) return hipSuccess;
     const int pb = cfg.persistent_blocks, pt = cfg.block_persistent;
+    const int cmp_tb = cfg.block_compact * cfg.items_compact;   // triangles per compaction tile
 
     H(K_INIT, 0);
     {
@@ -1259,7 +1274,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_RELINK, 0);
     GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
                     (sizeof(int) * 9 + 2 + 4) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
-                    rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap);
+                    rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, rb.status, cmp_tb);
     H(K_RELINK, 1);
 
     H(K_REPAIR, 0);
@@ -1272,13 +1287,18 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
-    hipLaunchKernelGGL(k_walk<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.walk, rb.walk_counts, rb.walk_cap);
+    hipLaunchKernelGGL(k_walk<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.walk, rb.walk_counts, rb.walk_cap,
+                       rb.status, cmp_tb);
     H(K_WALK, 1);
+
+    H(K_TSCAN, 0);
+    hipLaunchKernelGGL(k_tile_scan, dim3(rb.nmesh), dim3(1024), 0, s, rb.descs, rb.status, cmp_tb);
+    H(K_TSCAN, 1);
 
     H(K_COMPACT, 0);
     GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
                     sizeof(int) * 5 * (size_t)cfg.block_compact * cfg.items_compact, s, rb.descs, rb.nmesh,
-                    rb.rc, rb.status, rb.emit, rb.emit_counts, rb.emit_cap);
+                    rb.status, rb.emit, rb.emit_counts, rb.emit_cap);
     H(K_COMPACT, 1);
 
     H(K_EMIT, 0);

@@ -222,7 +222,7 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
         const int64_t nh = 3ll * m->nt;
         p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(m->nt + 1) +
                         arena_bytes<int32_t>(m->nt + 2);
-        p->tmp_mesh += arena_bytes<uint8_t>(align_up(m->nt + 4, 4)) + arena_bytes<uint8_t>(m->nt + 1);
+        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(m->nt + 4, 4));
     }
     if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
     p->cap_fix = 2 * p->cap_tips;
@@ -266,7 +266,7 @@ void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp
     rb->emit_cap = (int32_t)p.emit_cap;
     for (int i = 0; i < n; i++) {
         tflag[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));
-        pl[i] = at.take<uint8_t>(meshes[i]->nt + 1);
+        pl[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));   // whole words: k_walk claims by CAS
     }
 }
 
