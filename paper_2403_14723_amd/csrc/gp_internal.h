@@ -56,6 +56,7 @@ struct MeshDesc {
     int32_t *seeds;
     int32_t *loop_off;
     int32_t *loop_he;
+    int32_t *lpos;       // per triangle: where k_walk stored the loop whose minimum it holds
     MeshCounters *ctr;
     int32_t nt;
     int32_t nv;
@@ -88,8 +89,8 @@ constexpr int kStripePad = 32;   // counters 128 bytes apart: one cache line eac
 struct LaunchCfg {
     int block_label = 256, items_label = 4;
     int block_relink = 256, items_relink = 2;     // k_relink (tile <= 1024 triangles)
-    int block_compact = 512, items_compact = 4;   // tile <= 2048 triangles (LDS 20 B each)
-    int persistent_blocks = 1024;
+    int block_compact = 256, items_compact = 4;   // tile <= 2048 triangles (LDS 20 B each)
+    int persistent_blocks = 4096;
     int block_persistent = 256;
 };
 
@@ -111,7 +112,15 @@ struct RunBuffers {
     EmitEntry *emit;         // striped: loops k_compact leaves to k_emit
     int32_t *emit_counts;    // kStripes counters, kStripePad ints apart
     int32_t emit_cap;        // per stripe
+    int32_t *wbuf;           // striped: walked loops (rotation index, then half-edges)
+    int32_t *wbuf_counts;    // kStripes counters, kStripePad ints apart
+    int32_t wbuf_cap;        // ints per stripe
 };
+
+// k_walk records each chain's half-edges in LDS, up to this many; longer
+// loops are left to k_emit
+constexpr int kWalkBuf = 16;
+constexpr int kWalkItems = 2;   // chains per k_walk thread
 
 enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];

@@ -274,12 +274,13 @@ __device__ __forceinline__ void store_from_lds(gint dst, const int *src, int n) 
 // ---------------------------------------------------------------------------
 
 __global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t *status, int nstatus,
-                       int32_t *walk_counts, int32_t *emit_counts) {
+                       int32_t *walk_counts, int32_t *emit_counts, int32_t *wbuf_counts) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int stride = gridDim.x * blockDim.x;
     if (i < kStripes) {
         walk_counts[i * kStripePad] = 0;
         emit_counts[i * kStripePad] = 0;
+        wbuf_counts[i * kStripePad] = 0;
     }
     if (i == 0) {
         rc->ntips = 0;
@@ -378,17 +379,23 @@ constexpr int kPlQuadNext = 1;
 // the byte of the minimum's triangle adds the loop to the totals of that
 // triangle's compaction tile.  After a repair several seeds of one polygon
 // walk the same loop; only the first counts it.
-__device__ __forceinline__ void claim_loop(const MeshDesc &d, int mn, int len, uint64_t *agg, int cmp_tb) {
+__device__ __forceinline__ bool claim_loop(const MeshDesc &d, int mn, int len, uint64_t *agg, int cmp_tb) {
     const int tm = tri_of(mn);
     const uint32_t code = loop_code(mn, len);
     uint32_t *w = reinterpret_cast<uint32_t *>(d.pl) + (tm >> 2);
     const int sh = 8 * (tm & 3);
     // every walker of this loop writes the same code, so OR-ing it in is
     // safe; the one that found the byte empty counts the loop
-    if ((atomicOr(w, code << sh) >> sh) & 0xffu) return;
+    if ((atomicOr(w, code << sh) >> sh) & 0xffu) return false;
     atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + tm / cmp_tb),
               (1ull << 32) | (unsigned long long)(uint32_t)len);
+    return true;
 }
+
+// Label bit 6 of a loop's minimum triangle: k_walk stored the loop in the
+// scratch pool (at lpos of that triangle); k_relink writes the label bytes
+// with the bit clear.
+constexpr uint32_t kStoredBit = 1u << 6;
 
 // Copies n bytes from LDS src to global dst; both 4-byte aligned.
 __device__ __forceinline__ void store_bytes_from_lds(gu8 dst, const uint8_t *src, int n) {
@@ -877,24 +884,33 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
 // polygon (a frontier half-edge of the seed's own triangle if it has one),
 // around the loop, and the loop recorded.  Each thread keeps ITEMS loops in
 // flight and advances them in lock-step; each loop's next' array and bound
-// sit in registers.
-template <int ITEMS>
+// sit in registers.  Every chain also writes the half-edges it visits to an
+// LDS buffer, so the walker that claims a loop of at most BUF half-edges
+// copies it to the scratch pool (rotation index of the minimum, then the
+// half-edges in walk order) and k_compact places it without walking it
+// again.  Whole waves iterate together: the pool is reserved once per wave
+// and step.
+template <int ITEMS, int BUF>
 __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
                                               const int32_t *walk_counts, int walk_cap, uint64_t *agg,
-                                              int cmp_tb) {
+                                              int cmp_tb, int32_t *wbuf, int32_t *wbuf_counts, int wbuf_cap) {
+    constexpr int kSlots = 256 * ITEMS;
     __shared__ int s_pref[kStripes + 1];
+    __shared__ int s_buf[BUF * kSlots];   // element k of chain slot q at k * kSlots + q
     const int total = striped_prefix(walk_counts, walk_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
-    for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
+    const int lane = __lane_id(), tid = threadIdx.x;
+    const int wstripe = ((blockIdx.x * blockDim.x + tid) >> 6) % kStripes;   // this wave's pool stripe
+    for (int b0 = blockIdx.x * blockDim.x; b0 < total; b0 += nthreads * ITEMS) {   // block-uniform
         gcint nx[ITEMS];
-        int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], len[ITEMS], lim[ITEMS];
+        int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], rot[ITEMS], len[ITEMS], lim[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             start[j] = cur[j] = mn[j] = -1;
-            len[j] = lim[j] = 0;
+            rot[j] = len[j] = lim[j] = 0;
             mesh[j] = 0;
             nx[j] = nullptr;
-            const int g = g0 + j * nthreads;
+            const int g = b0 + tid + j * nthreads;
             if (g >= total) continue;
             const ListEntry e = walk[striped_index(s_pref, walk_cap, g)];
             const MeshDesc &d = descs[e.mesh];
@@ -914,13 +930,18 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
             }
             start[j] = cur[j] = mn[j] = st;
         }
-        bool active = true;
-        while (active) {
-            active = false;
+        while (true) {
+            bool active = false;
+            int need[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
+                need[j] = 0;
                 if (start[j] < 0) continue;
-                mn[j] = cur[j] < mn[j] ? cur[j] : mn[j];
+                if (len[j] < BUF) s_buf[len[j] * kSlots + j * 256 + tid] = cur[j];
+                if (cur[j] < mn[j]) {
+                    mn[j] = cur[j];
+                    rot[j] = len[j];
+                }
                 ++len[j];
                 cur[j] = nx[j][cur[j]];
                 if (cur[j] < 0 || len[j] > lim[j]) {
@@ -929,12 +950,44 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                     continue;
                 }
                 if (cur[j] == start[j]) {
-                    claim_loop(descs[mesh[j]], mn[j], len[j], agg, cmp_tb);
+                    const bool win = claim_loop(descs[mesh[j]], mn[j], len[j], agg, cmp_tb);
+                    // whole 16-byte groups, so k_compact reads a loop with vector loads
+                    need[j] = win && len[j] <= BUF ? (len[j] + 4) & ~3 : 0;
                     start[j] = -1;
                     continue;
                 }
                 active = true;
             }
+            // pool space for the loops claimed in this step: one atomic per wave
+            int mine = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) mine += need[j];
+            int incl = mine;
+#pragma unroll
+            for (int dd = 1; dd < kWave; dd <<= 1) {
+                const int y = __shfl_up(incl, dd);
+                if (lane >= dd) incl += y;
+            }
+            const int wtot = __shfl(incl, kWave - 1);
+            int wbase = 0;
+            if (lane == 0 && wtot > 0) wbase = atomicAdd(&wbuf_counts[wstripe * kStripePad], wtot);
+            wbase = __shfl(wbase, 0);
+            if (mine > 0 && wbase + wtot <= wbuf_cap) {
+                int pos = wstripe * wbuf_cap + wbase + incl - mine;
+#pragma unroll
+                for (int j = 0; j < ITEMS; j++) {
+                    if (!need[j]) continue;
+                    const MeshDesc &d = descs[mesh[j]];
+                    const gint out = (gint)wbuf + pos;
+                    out[0] = rot[j];
+                    for (int k = 0; k < len[j]; k++) out[1 + k] = s_buf[k * kSlots + j * 256 + tid];
+                    const int tm = tri_of(mn[j]);
+                    ((gint)d.lpos)[tm] = pos;
+                    atomicOr(reinterpret_cast<uint32_t *>(d.tflag) + (tm >> 2), kStoredBit << (8 * (tm & 3)));
+                    pos += need[j];
+                }
+            }
+            if (!__any(active)) break;
         }
     }
 }
@@ -1013,6 +1066,37 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__
     const int B = blockDim.x, tid = threadIdx.x;
     const int per = (ntiles + B - 1) / B;
     const int k0 = min(tid * per, ntiles), k1 = min(k0 + per, ntiles);
+    constexpr int kPer = 32;
+    if (per <= kPer) {   // up to 32K tiles: every value loaded once, all in flight
+        uint64_t v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; u++) v[u] = st[min(k0 + u, ntiles - 1)];
+        int c = 0, h = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (k0 + u >= k1) v[u] = 0ull;
+            c += (int)(v[u] >> 32);
+            h += (int)(uint32_t)v[u];
+        }
+        int ec, eh, tc, th;
+        block_excl_scan2(c, h, ec, eh, tc, th, s_scan);
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            if (k0 + u < k1) st[k0 + u] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
+            ec += (int)(v[u] >> 32);
+            eh += (int)(uint32_t)v[u];
+        }
+        if (tid == 0) {
+            const bool ok = tc >= 0 && th >= 0 && tc <= d.nt && th <= 3 * d.nt;
+            d.ctr->npoly = ok ? tc : 0;
+            d.ctr->nloop = ok ? th : 0;
+            if (ok)
+                d.loop_off[tc] = th;
+            else
+                atomicOr(&d.ctr->err, kErrCorrupt);
+        }
+        return;
+    }
     // eight loads in flight per thread (indices clamped, values masked)
     int c = 0, h = 0;
     for (int k = k0; k < k1; k += 8) {
@@ -1072,7 +1156,7 @@ __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
                                                   const uint64_t *status, EmitEntry *emit, int32_t *emit_counts,
-                                                  int emit_cap) {
+                                                  int emit_cap, const int32_t *wbuf) {
     // LDS: loop half-edges (3 per triangle of the tile), seeds and local
     // offsets (one per triangle)
     extern __shared__ int4 lds_raw[];
@@ -1096,7 +1180,8 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     const int pc = (int)(pre >> 32), ps = (int)(uint32_t)pre;
 
     // 1. loop minima and lengths of this thread's ITEMS contiguous triangles;
-    //    which loops k_emit writes (longer than a quad)
+    //    which loops are longer than a quad, and which of those k_walk stored
+    //    (the rest k_emit writes)
     uint8_t code[ITEMS], fl[ITEMS];
     if (ITEMS == 4 && t0 + 4 <= nt) {
         const uint32_t w = *reinterpret_cast<GLOBAL const uint32_t *>(plb + t0);
@@ -1134,7 +1219,7 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         defer[j] = len > 0 && len != 3 && !(len == 4 && __popc((fl[j] >> 2) & 7u) == 2);
         cnt += 1;
         sum += len;
-        nd += defer[j];
+        nd += defer[j] && !(fl[j] & kStoredBit);
     }
     // 2. block scan: tile-local loop index and offset, emit-list slot
     int ecn, esum, tcn, tsum;
@@ -1207,6 +1292,29 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
                     he_out[off + 2] = he_next(p1);
                     he_out[off + 3] = aa;
                 }
+            } else if (defer[j] && (fl[j] & kStoredBit)) {
+                // stored by k_walk in walk order from some start; rotate so
+                // the loop begins at its minimum (loads first, all in flight)
+                static_assert(kWalkBuf % 4 == 0, "stored loops are read in 16-byte groups");
+                const int len = lens[j];
+                const GLOBAL v4i *src = (GLOBAL const v4i *)((gcint)wbuf + ((gcint)d.lpos)[t]);
+                v4i g[kWalkBuf / 4 + 1];   // rotation index, then the half-edges
+#pragma unroll
+                for (int c = 0; c <= kWalkBuf / 4; c++) g[c] = src[c];
+                int v[kWalkBuf + 4];
+#pragma unroll
+                for (int c = 0; c <= kWalkBuf / 4; c++) {
+                    v[4 * c] = g[c].x;
+                    v[4 * c + 1] = g[c].y;
+                    v[4 * c + 2] = g[c].z;
+                    v[4 * c + 3] = g[c].w;
+                }
+                const int rot = v[0];
+                if (rot < 0 || rot >= len || len > kWalkBuf || v[1 + rot] != mn) bad = true;
+                else
+#pragma unroll
+                    for (int k = 0; k < kWalkBuf; k++)
+                        if (k < len) he_out[off + (k >= rot ? k - rot : k - rot + len)] = v[1 + k];
             } else if (defer[j]) {
                 if (e < elim) {
                     emit[e].mesh = mi;
@@ -1262,7 +1370,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
         int grid = (n + 255) / 256;
         grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
         hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, rb.rc, rb.ctrs, rb.nmesh, rb.status,
-                           rb.cmp_tiles, rb.walk_counts, rb.emit_counts);
+                           rb.cmp_tiles, rb.walk_counts, rb.emit_counts, rb.wbuf_counts);
     }
     H(K_INIT, 1);
 
@@ -1287,8 +1395,8 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
-    hipLaunchKernelGGL(k_walk<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.walk, rb.walk_counts, rb.walk_cap,
-                       rb.status, cmp_tb);
+    hipLaunchKernelGGL((k_walk<kWalkItems, kWalkBuf>), dim3(pb), dim3(256), 0, s, rb.descs, rb.walk,
+                       rb.walk_counts, rb.walk_cap, rb.status, cmp_tb, rb.wbuf, rb.wbuf_counts, rb.wbuf_cap);
     H(K_WALK, 1);
 
     H(K_TSCAN, 0);
@@ -1298,7 +1406,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_COMPACT, 0);
     GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
                     sizeof(int) * 5 * (size_t)cfg.block_compact * cfg.items_compact, s, rb.descs, rb.nmesh,
-                    rb.status, rb.emit, rb.emit_counts, rb.emit_cap);
+                    rb.status, rb.emit, rb.emit_counts, rb.emit_cap, rb.wbuf);
     H(K_COMPACT, 1);
 
     H(K_EMIT, 0);

@@ -196,7 +196,7 @@ struct Plan {
     std::vector<gp::MeshDesc> descs;   // sizes and tile offsets filled in
     std::vector<int32_t> nts;
     int64_t tri_tiles = 0, he_tiles = 0, cmp_tiles = 0, cap_tips = 0, cap_fix = 0;
-    int64_t walk_cap = 0, emit_cap = 0;
+    int64_t walk_cap = 0, emit_cap = 0, wbuf_cap = 0;
     size_t out_bytes = 0, tmp_bytes = 0, tmp_mesh = 0;
 };
 
@@ -222,7 +222,7 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
         const int64_t nh = 3ll * m->nt;
         p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(m->nt + 1) +
                         arena_bytes<int32_t>(m->nt + 2);
-        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(m->nt + 4, 4));
+        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(m->nt + 4, 4)) + arena_bytes<int32_t>(m->nt + 1);
     }
     if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
     p->cap_fix = 2 * p->cap_tips;
@@ -231,17 +231,23 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
     const int64_t S = gp::kStripes;
     p->walk_cap = (p->he_tiles + S - 1) / S * th + (2 * p->cap_tips + S - 1) / S + 2;
     p->emit_cap = (p->cmp_tiles + S - 1) / S * tc;
-    if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff) return GP_ERANGE;
+    // walked loops: at most 3T half-edges in all (each loop is stored once)
+    // plus one rotation index per loop; slack for uneven stripes
+    int64_t total_nt = 0;
+    for (int i = 0; i < n; i++) total_nt += meshes[i]->nt;
+    p->wbuf_cap = align_up((4 * total_nt + S - 1) / S + 4096, 4);
+    if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff || p->wbuf_cap * S > 0x7fffffff)
+        return GP_ERANGE;
     p->tmp_bytes = p->tmp_mesh + arena_bytes<gp::MeshDesc>(n) + arena_bytes<gp::RunCounters>(1) +
                    arena_bytes<gp::MeshCounters>(n) + arena_bytes<gp::ListEntry>(p->cap_tips) +
                    arena_bytes<gp::ListEntry>(p->cap_fix) + arena_bytes<uint64_t>(p->cmp_tiles) +
                    arena_bytes<gp::ListEntry>(p->walk_cap * S) + arena_bytes<gp::EmitEntry>(p->emit_cap * S) +
-                   2 * arena_bytes<int32_t>(S * gp::kStripePad);
+                   arena_bytes<int32_t>(p->wbuf_cap * S + 32) + 3 * arena_bytes<int32_t>(S * gp::kStripePad);
     return GP_OK;
 }
 
 void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp::RunBuffers *rb,
-                    uint8_t **tflag, uint8_t **pl) {
+                    uint8_t **tflag, uint8_t **pl, int32_t **lpos) {
     const int n = (int)p.descs.size();
     const int64_t S = gp::kStripes;
     Arena at{static_cast<char *>(block), p.tmp_bytes, 0};
@@ -264,9 +270,13 @@ void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp
     rb->emit = at.take<gp::EmitEntry>(p.emit_cap * S);
     rb->emit_counts = at.take<int32_t>(S * gp::kStripePad);
     rb->emit_cap = (int32_t)p.emit_cap;
+    rb->wbuf = at.take<int32_t>(p.wbuf_cap * S + 32);   // + a 16-byte-group overread at the end
+    rb->wbuf_counts = at.take<int32_t>(S * gp::kStripePad);
+    rb->wbuf_cap = (int32_t)p.wbuf_cap;
     for (int i = 0; i < n; i++) {
         tflag[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));
-        pl[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));   // whole words: k_walk claims by CAS
+        pl[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));   // whole words: k_walk claims by OR
+        lpos[i] = at.take<int32_t>(meshes[i]->nt + 1);
     }
 }
 
@@ -310,6 +320,7 @@ struct GraphEntry {
     void *scratch = nullptr;
     gp::RunBuffers rb{};
     std::vector<uint8_t *> tflag, pl;
+    std::vector<int32_t *> lpos;
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
 };
@@ -360,6 +371,7 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     const int n = (int)plan.nts.size();
     e.tflag.resize(n);
     e.pl.resize(n);
+    e.lpos.resize(n);
     // layout_scratch only needs the sizes of the meshes
     std::vector<gp_mesh> shapes(n);
     std::vector<const gp_mesh *> ptrs(n);
@@ -367,7 +379,7 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
         shapes[i].nt = plan.nts[i];
         ptrs[i] = &shapes[i];
     }
-    layout_scratch(plan, e.scratch, ptrs.data(), &e.rb, e.tflag.data(), e.pl.data());
+    layout_scratch(plan, e.scratch, ptrs.data(), &e.rb, e.tflag.data(), e.pl.data(), e.lpos.data());
     hipGraph_t graph = nullptr;
     hipStream_t s = c->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -777,12 +789,14 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     }
     gp::RunBuffers rb{};
     std::vector<uint8_t *> tflag(n), pl(n);
+    std::vector<int32_t *> lpos(n);
     if (ge) {
         rb = ge->rb;
         tflag = ge->tflag;
         pl = ge->pl;
+        lpos = ge->lpos;
     } else {
-        layout_scratch(plan, p_tmp, meshes, &rb, tflag.data(), pl.data());
+        layout_scratch(plan, p_tmp, meshes, &rb, tflag.data(), pl.data(), lpos.data());
     }
     Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
     std::vector<gp_result *> res(n, nullptr);
@@ -820,6 +834,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         d.loop_he = x->loop_he;
         d.tflag = tflag[i];
         d.pl = pl[i];
+        d.lpos = lpos[i];
         d.ctr = rb.ctrs + i;
     }
     hipStream_t s = c->stream;
