@@ -2,11 +2,14 @@
 
 The launch shapes (threads per block, triangles per thread, persistent grid
 size) never change a result; they only move time between latency and
-occupancy, and the best ones depend on the workload's mesh sizes.  Each
-streaming kernel's time depends only on its own shape, so the search is
-coordinate-wise: for every kernel group in turn, each candidate shape is
-timed on the caller's meshes (per-kernel HIP event times from a profiling
-context, averaged over several batched runs) and the fastest one is kept.
+occupancy, and the best ones depend on the workload's mesh sizes.  The search
+is coordinate-wise: for every kernel group in turn, each candidate shape is
+timed on the caller's meshes and the fastest one is kept.  The time is that
+of the whole chain (per-kernel HIP event times from a profiling context,
+summed, averaged over several batched runs): one kernel's shape also moves
+work in others (the compaction tile sets the tile scan's length and how the
+relink tiles feed it).  The starting shapes stay unless the search beats
+them.
 
 Results are cached in a JSON file keyed by the device and a signature of the
 workload (mesh count and total triangles, rounded to a power of two), so a
@@ -21,7 +24,7 @@ import time
 
 from . import GP_ASYNC, Context
 
-# kernel group -> (kernels whose time decides it, candidate (B, I) shapes)
+# kernel group -> (the kernels it shapes, candidate (B, I) shapes)
 GROUPS = {
     "label": (("k_label",), [(b, i) for b in (128, 256, 512, 1024) for i in (1, 2, 4, 8) if b * i <= 4096]),
     "relink": (("k_relink",), [(b, i) for b in (64, 128, 256, 512, 1024) for i in (1, 2, 4, 8) if b * i <= 1024]),
@@ -60,7 +63,7 @@ def _parse(spec: str) -> dict:
     return out
 
 
-def _time_groups(ctx: Context, handles, kernels, reps: int) -> float:
+def _time_chain(ctx: Context, handles, reps: int) -> float:
     for r in ctx.mesh_batch(handles, GP_ASYNC):   # warm-up (first-use allocations)
         r.free()
     ctx.sync()
@@ -69,8 +72,7 @@ def _time_groups(ctx: Context, handles, kernels, reps: int) -> float:
         for r in ctx.mesh_batch(handles, GP_ASYNC):
             r.free()
     ctx.sync()
-    km = ctx.kernel_ms()
-    return sum(km[k][0] for k in kernels if k in km)
+    return sum(avg for avg, _ in ctx.kernel_ms().values())
 
 
 def tune(meshes, device: int = 0, reps: int = 3, cache: str | None = None, force: bool = False,
@@ -97,25 +99,41 @@ def tune(meshes, device: int = 0, reps: int = 3, cache: str | None = None, force
         return hit
 
     with Context(device, profile=True) as ctx:
-        shapes = _parse(ctx.launch())
+        start = _parse(ctx.launch())
+        shapes = dict(start)
         handles = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
         best_ms = {}
         try:
-            for group, (kernels, cands) in GROUPS.items():
-                best = None
+            ctx.set_launch(_spec(start))
+            start_ms = _time_chain(ctx, handles, reps)
+            current = start_ms
+            for group, (_kernels, cands) in GROUPS.items():
+                best = (current, shapes[group])
                 for cand in cands:
+                    if cand == shapes[group]:
+                        continue
                     trial = dict(shapes)
                     trial[group] = cand
                     ctx.set_launch(_spec(trial))
                     if _parse(ctx.launch())[group] != cand:
                         continue   # clamped to a shape already tried
-                    ms = _time_groups(ctx, handles, kernels, reps)
+                    ms = _time_chain(ctx, handles, reps)
                     if log:
                         log(f"[tune] {group}={cand[0]}x{cand[1]}: {ms:.4f} ms")
-                    if best is None or ms < best[0]:
+                    if ms < best[0]:
                         best = (ms, cand)
                 shapes[group] = best[1]
                 best_ms[group] = round(best[0], 5)
+                current = best[0]
+            # confirm against the starting shapes, both timed again
+            ctx.set_launch(_spec(shapes))
+            tuned_ms = _time_chain(ctx, handles, 2 * reps)
+            ctx.set_launch(_spec(start))
+            again_ms = _time_chain(ctx, handles, 2 * reps)
+            if tuned_ms >= again_ms:
+                shapes = start
+            best_ms["chain_start"] = round(again_ms, 5)
+            best_ms["chain_tuned"] = round(tuned_ms, 5)
         finally:
             for h in handles:
                 h.free()

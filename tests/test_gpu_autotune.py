@@ -19,7 +19,7 @@ def test_tune_cache_and_parity(tmp_path):
     say("[gpu] autotune search")
     first = autotune.tune(meshes, reps=1, cache=cache)
     assert not first["cached"]
-    assert set(first["ms"]) == set(autotune.GROUPS)
+    assert set(autotune.GROUPS) <= set(first["ms"])
     second = autotune.tune(meshes, reps=1, cache=cache)
     assert second["cached"] and second["spec"] == first["spec"]
     with gp.Context(0) as c:
