@@ -66,6 +66,8 @@ struct MeshDesc {
     int32_t pad;
 };
 
+static_assert(sizeof(MeshDesc) % 4 == 0, "descriptor tables are copied in 4-byte words");
+
 struct ListEntry {
     int32_t mesh;
     int32_t he;
@@ -130,6 +132,10 @@ typedef void (*launch_hook)(void *user, int kernel_id, int after);
 
 hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s,
                            launch_hook hook, void *user);
+
+// Copies `bytes` (a multiple of 4) with a kernel on stream s; either side may
+// be coherent pinned host memory.
+hipError_t launch_copy_words(void *dst, const void *src, size_t bytes, hipStream_t s);
 
 // tiles of one mesh for a given tile size; every mesh has at least one tile
 // so that an empty mesh still gets its loop_off[0] written

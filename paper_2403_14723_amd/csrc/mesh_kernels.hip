@@ -1341,6 +1341,26 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// small copies between device memory and coherent pinned host memory (the
+// descriptor table before a run, the per-mesh counters after it): a kernel
+// in stream order instead of the runtime's copy path
+// ---------------------------------------------------------------------------
+
+__global__ void k_copy_words(uint32_t *dst, const uint32_t *src, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_copy_words(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes % 4 || bytes / 4 > 0x7fffffff) return hipErrorInvalidValue;
+    const int n = (int)(bytes / 4);
+    if (n == 0) return hipSuccess;
+    const int grid = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_copy_words, dim3(grid), dim3(256), 0, s, static_cast<uint32_t *>(dst),
+                       static_cast<const uint32_t *>(src), n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // host launch of the whole chain
 // ---------------------------------------------------------------------------
 
