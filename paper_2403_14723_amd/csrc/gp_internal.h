@@ -32,7 +32,7 @@ struct MeshCounters {
     int32_t nties;
     int32_t npoly;
     int32_t nloop;
-    int32_t pad;
+    int32_t chunks_done;   // k_tile_scan blocks finished (the last one scans the chunk totals)
 };
 
 // list sizes and the dynamic tile counter of one run
@@ -106,7 +106,9 @@ struct RunBuffers {
     ListEntry *tips;         // capacity cap_tips
     ListEntry *fixes;        // capacity cap_fix
     int32_t cap_tips, cap_fix;
-    uint64_t *status;        // per compaction tile: (loops << 32 | half-edges), then its exclusive prefix
+    uint64_t *status;        // per compaction tile: (loops << 32 | half-edges), then its prefix within its chunk
+    uint64_t *cpre;          // per compaction tile; at each chunk's first tile: the chunk's prefix
+    int32_t max_chunks;      // most chunks (of kScanChunk tiles) in one mesh
     MeshCounters *ctrs;      // device, nmesh entries
     ListEntry *walk;         // striped: seeds left open by k_relink and repair seeds
     int32_t *walk_counts;    // kStripes counters, kStripePad ints apart
@@ -123,6 +125,7 @@ struct RunBuffers {
 // loops are left to k_emit
 constexpr int kWalkBuf = 16;
 constexpr int kWalkItems = 2;   // chains per k_walk thread
+constexpr int kScanChunk = 1024;   // compaction tiles per k_tile_scan block
 
 enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];

@@ -1058,78 +1058,49 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__ descs, uint64_t *status,
-                                                     int cmp_tb) {
+                                                     uint64_t *cpre, int cmp_tb) {
+    // block (mesh, chunk): tiles [chunk * kScanChunk, ...) of that mesh, one
+    // per thread, read and written contiguously
     __shared__ int s_scan[72];
+    __shared__ int s_last;
     const MeshDesc &d = descs[blockIdx.x];
     const int ntiles = d.nt > 0 ? (d.nt + cmp_tb - 1) / cmp_tb : 1;
+    const int nchunks = (ntiles + kScanChunk - 1) / kScanChunk;
+    const int chunk = blockIdx.y;
+    if (chunk >= nchunks) return;   // the whole block
+    const int tid = threadIdx.x, k = chunk * kScanChunk + tid;
     uint64_t *st = status + d.cmp_tile0;
-    const int B = blockDim.x, tid = threadIdx.x;
-    const int per = (ntiles + B - 1) / B;
-    const int k0 = min(tid * per, ntiles), k1 = min(k0 + per, ntiles);
-    constexpr int kPer = 32;
-    if (per <= kPer) {   // up to 32K tiles: every value loaded once, all in flight
-        uint64_t v[kPer];
-#pragma unroll
-        for (int u = 0; u < kPer; u++) v[u] = st[min(k0 + u, ntiles - 1)];
-        int c = 0, h = 0;
-#pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            if (k0 + u >= k1) v[u] = 0ull;
-            c += (int)(v[u] >> 32);
-            h += (int)(uint32_t)v[u];
-        }
-        int ec, eh, tc, th;
-        block_excl_scan2(c, h, ec, eh, tc, th, s_scan);
-#pragma unroll
-        for (int u = 0; u < kPer; u++) {
-            if (k0 + u < k1) st[k0 + u] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
-            ec += (int)(v[u] >> 32);
-            eh += (int)(uint32_t)v[u];
-        }
-        if (tid == 0) {
-            const bool ok = tc >= 0 && th >= 0 && tc <= d.nt && th <= 3 * d.nt;
-            d.ctr->npoly = ok ? tc : 0;
-            d.ctr->nloop = ok ? th : 0;
-            if (ok)
-                d.loop_off[tc] = th;
-            else
-                atomicOr(&d.ctr->err, kErrCorrupt);
-        }
-        return;
-    }
-    // eight loads in flight per thread (indices clamped, values masked)
-    int c = 0, h = 0;
-    for (int k = k0; k < k1; k += 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) v[u] = st[min(k + u, k1 - 1)];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const uint64_t x = k + u < k1 ? v[u] : 0ull;
-            c += (int)(x >> 32);
-            h += (int)(uint32_t)x;
-        }
-    }
+    const uint64_t v = k < ntiles ? st[k] : 0ull;
     int ec, eh, tc, th;
-    block_excl_scan2(c, h, ec, eh, tc, th, s_scan);
-    for (int k = k0; k < k1; k += 8) {
-        uint64_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) v[u] = st[min(k + u, k1 - 1)];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            if (k + u >= k1) break;
-            st[k + u] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
-            ec += (int)(v[u] >> 32);
-            eh += (int)(uint32_t)v[u];
-        }
+    block_excl_scan2((int)(v >> 32), (int)(uint32_t)v, ec, eh, tc, th, s_scan);
+    if (k < ntiles) st[k] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
+    // chunk total at the chunk's first tile; the last block of the mesh turns
+    // the totals into prefixes
+    if (tid == 0) {
+        cpre[d.cmp_tile0 + chunk * kScanChunk] = ((uint64_t)(uint32_t)tc << 32) | (uint32_t)th;
+        __threadfence();
+        s_last = atomicAdd(&d.ctr->chunks_done, 1) == nchunks - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    int c = 0, h = 0;
+    for (int base = 0; base < nchunks; base += blockDim.x) {   // chunks beyond 1024: further rounds
+        const int q = base + tid;
+        uint64_t *slot = cpre + d.cmp_tile0 + (size_t)q * kScanChunk;
+        const uint64_t w = q < nchunks ? __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+        int ec2, eh2, tc2, th2;
+        block_excl_scan2((int)(w >> 32), (int)(uint32_t)w, ec2, eh2, tc2, th2, s_scan);
+        if (q < nchunks) *slot = ((uint64_t)(uint32_t)(c + ec2) << 32) | (uint32_t)(h + eh2);
+        c += tc2;
+        h += th2;
     }
     if (tid == 0) {
-        const bool ok = tc >= 0 && th >= 0 && tc <= d.nt && th <= 3 * d.nt;
-        d.ctr->npoly = ok ? tc : 0;
-        d.ctr->nloop = ok ? th : 0;
+        const bool ok = c >= 0 && h >= 0 && c <= d.nt && h <= 3 * d.nt;
+        d.ctr->npoly = ok ? c : 0;
+        d.ctr->nloop = ok ? h : 0;
         if (ok)
-            d.loop_off[tc] = th;
+            d.loop_off[c] = h;
         else
             atomicOr(&d.ctr->err, kErrCorrupt);
     }
@@ -1155,8 +1126,8 @@ __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
 
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
-                                                  const uint64_t *status, EmitEntry *emit, int32_t *emit_counts,
-                                                  int emit_cap, const int32_t *wbuf) {
+                                                  const uint64_t *status, const uint64_t *cpre, EmitEntry *emit,
+                                                  int32_t *emit_counts, int emit_cap, const int32_t *wbuf) {
     // LDS: loop half-edges (3 per triangle of the tile), seeds and local
     // offsets (one per triangle)
     extern __shared__ int4 lds_raw[];
@@ -1176,7 +1147,8 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     const int t0 = ltile * TB + tid * ITEMS;
     const gcint nx = (gcint)d.next_o;
     const gcu8 plb = (gcu8)d.pl, tfl = (gcu8)d.tflag;
-    const uint64_t pre = status[tile];
+    // prefix within the chunk plus the chunk's prefix (no field carries)
+    const uint64_t pre = status[tile] + cpre[d.cmp_tile0 + ltile / kScanChunk * kScanChunk];
     const int pc = (int)(pre >> 32), ps = (int)(uint32_t)pre;
 
     // 1. loop minima and lengths of this thread's ITEMS contiguous triangles;
@@ -1420,13 +1392,14 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_WALK, 1);
 
     H(K_TSCAN, 0);
-    hipLaunchKernelGGL(k_tile_scan, dim3(rb.nmesh), dim3(1024), 0, s, rb.descs, rb.status, cmp_tb);
+    hipLaunchKernelGGL(k_tile_scan, dim3(rb.nmesh, rb.max_chunks), dim3(1024), 0, s, rb.descs, rb.status,
+                       rb.cpre, cmp_tb);
     H(K_TSCAN, 1);
 
     H(K_COMPACT, 0);
     GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
                     sizeof(int) * 5 * (size_t)cfg.block_compact * cfg.items_compact, s, rb.descs, rb.nmesh,
-                    rb.status, rb.emit, rb.emit_counts, rb.emit_cap, rb.wbuf);
+                    rb.status, rb.cpre, rb.emit, rb.emit_counts, rb.emit_cap, rb.wbuf);
     H(K_COMPACT, 1);
 
     H(K_EMIT, 0);

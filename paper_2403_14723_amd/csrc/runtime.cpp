@@ -244,7 +244,7 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
         return GP_ERANGE;
     p->tmp_bytes = p->tmp_mesh + arena_bytes<gp::MeshDesc>(n) + arena_bytes<gp::RunCounters>(1) +
                    arena_bytes<gp::MeshCounters>(n) + arena_bytes<gp::ListEntry>(p->cap_tips) +
-                   arena_bytes<gp::ListEntry>(p->cap_fix) + arena_bytes<uint64_t>(p->cmp_tiles) +
+                   arena_bytes<gp::ListEntry>(p->cap_fix) + 2 * arena_bytes<uint64_t>(p->cmp_tiles) +
                    arena_bytes<gp::ListEntry>(p->walk_cap * S) + arena_bytes<gp::EmitEntry>(p->emit_cap * S) +
                    arena_bytes<int32_t>(p->wbuf_cap * S + 32) + 3 * arena_bytes<int32_t>(S * gp::kStripePad);
     return GP_OK;
@@ -268,6 +268,17 @@ void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp
     rb->cap_tips = (int32_t)p.cap_tips;
     rb->cap_fix = (int32_t)p.cap_fix;
     rb->status = at.take<uint64_t>(p.cmp_tiles);
+    rb->cpre = at.take<uint64_t>(p.cmp_tiles);
+    {
+        const int64_t tc = (int64_t)p.cmp_tiles;   // (tiles of each mesh are in descs)
+        int64_t mc = 1;
+        for (int i = 0; i < n; i++) {
+            const int64_t end = i + 1 < n ? p.descs[i + 1].cmp_tile0 : tc;
+            const int64_t nt_tiles = end - p.descs[i].cmp_tile0;
+            mc = std::max<int64_t>(mc, (nt_tiles + gp::kScanChunk - 1) / gp::kScanChunk);
+        }
+        rb->max_chunks = (int32_t)mc;
+    }
     rb->walk = at.take<gp::ListEntry>(p.walk_cap * S);
     rb->walk_counts = at.take<int32_t>(S * gp::kStripePad);
     rb->walk_cap = (int32_t)p.walk_cap;
