@@ -139,6 +139,46 @@ def bench_batched(gp, W, stream, steps):
     return out
 
 
+def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
+    """The general-position workload (the paper's Random meshes): a Delaunay
+    triangulation of random points, numbered along a Z-order curve, meshed on
+    the device like the plain workload (graph replay)."""
+    import torch
+    t0 = time.perf_counter()
+    m = W.random_delaunay(npts, seed=21, order="morton")
+    gen_s = time.perf_counter() - t0
+    ctx = gp.Context(0, stream=stream.cuda_stream)
+    h = ctx.build_halfedges(m.xy, m.tri)
+    flags = gp.GP_ASYNC | gp.GP_GRAPH
+    for _ in range(3):
+        ctx.mesh(h, flags).free()
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.mesh(h, flags).free()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    r = ctx.mesh(h)
+    info = r.info()
+    r.free()
+    pctx = gp.Context(0, stream=stream.cuda_stream, profile=True)
+    ph = pctx.build_halfedges(m.xy, m.tri)
+    for _ in range(max(3, steps // 2)):
+        pctx.mesh(ph, gp.GP_ASYNC).free()
+    pctx.sync()
+    kms = {k: round(v[0], 5) for k, v in pctx.kernel_ms().items()}
+    ph.free()
+    pctx.close()
+    h.free()
+    ctx.close()
+    return {"workload": m.name, "triangles": m.nt, "vertices": m.nv, "polygons": info["npoly"],
+            "loop_half_edges": info["nloop_he"], "tips": info["ntips"], "ms_per_step": round(ms, 4),
+            "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms, "generate_s": round(gen_s, 1)}
+
+
 def bench_served(gp, W, n_req=2000, warm=64, cap_n=256, rhos=(0.5, 0.8)):
     """Continuous-batching server: capacity from a closed loop, then Poisson
     arrivals at rho * capacity; latency = submit -> result on the host."""
@@ -321,8 +361,11 @@ def main():
     value = nt / (ms_per_step * 1e-3) / 1e6
     traffic, traffic_src = measured_traffic(dom.split("<")[0])
 
-    batched = served = None
+    batched = served = delaunay = None
     if not args.no_forms:
+        log("[bench] general-position workload (Delaunay, 1M points)")
+        delaunay = bench_delaunay(gp, W, stream, max(5, args.steps // 2))
+        log(f"[bench] {delaunay}")
         log("[bench] batched vs plain (512 meshes)")
         batched = bench_batched(gp, W, stream, max(3, args.steps // 4))
         log(f"[bench] {batched}")
@@ -361,6 +404,7 @@ def main():
                      "with_copies_mtri_s": round(nt / ((h2d_ms + build_ms + ms_per_step + d2h_ms) * 1e-3) / 1e6, 2)},
         "batched": batched,
         "served": served,
+        "delaunay": delaunay,
         "cpu_baseline": cpu,
     }
     if check is not None:

@@ -452,7 +452,13 @@ __device__ __forceinline__ int run_turn(const TileLabels &T, int c, int Lc, bool
     return -1;
 }
 
-// Appends barrier tip he of mesh mi to the tip list (tips are rare).
+// Records a barrier tip found in a k_relink tile in the tile's LDS list
+// (appended to the global list once per block); straight to the global list
+// when the LDS list is full.
+__device__ __forceinline__ void tile_tip(int *s_tip, int *s_ntip, int tcap, int local_he, int base, RunCounters *rc,
+                                         ListEntry *tips, int cap_tips, const MeshDesc &d, int mi, bool &err);
+
+// Appends barrier tip he of mesh mi to the tip list.
 __device__ __forceinline__ void push_tip(RunCounters *rc, ListEntry *tips, int cap_tips, const MeshDesc &d, int mi,
                                          int he, bool &err) {
     const int slot = atomicAdd(&rc->ntips, 1);
@@ -463,6 +469,15 @@ __device__ __forceinline__ void push_tip(RunCounters *rc, ListEntry *tips, int c
     } else {
         err = true;
     }
+}
+
+__device__ __forceinline__ void tile_tip(int *s_tip, int *s_ntip, int tcap, int local_he, int base, RunCounters *rc,
+                                         ListEntry *tips, int cap_tips, const MeshDesc &d, int mi, bool &err) {
+    const int i = atomicAdd(s_ntip, 1);
+    if (i < tcap)
+        s_tip[i] = local_he;
+    else
+        push_tip(rc, tips, cap_tips, d, mi, 3 * base + local_he, err);
 }
 
 // Frontier bit of half-edge c of a triangle outside the tile whose
@@ -489,6 +504,10 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     uint8_t *s_pl = s_f + TB;                                   // loop bytes
     int *s_q = reinterpret_cast<int *>(s_pl + TB);              // queued turns, 2 ints each
     const int qcap = TB / 2;
+    int *s_tip = s_q + 2 * qcap;                                // barrier tips found here
+    const int tcap = TB / 4;
+    __shared__ int s_ntip;
+    if (threadIdx.x == 0) s_ntip = 0;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<1>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
@@ -595,7 +614,7 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             s_nx[3 * lt + na] = cn;
             // next'(h) == twin(h): the target of h is a barrier tip
             if (cn == (na == 0 ? tw[j][0] : (na == 1 ? tw[j][1] : tw[j][2])))
-                push_tip(rc, tips, cap_tips, d, mi, h0 + na, err);
+                tile_tip(s_tip, &s_ntip, tcap, 3 * lt + na, base, rc, tips, cap_tips, d, mi, err);
         }
         if (hitq) s_pv[3 * lt + pa] = cp;
         pend |= (mn && !hitn ? 1u : 0u) << (2 * j) | (mp && !hitq ? 1u : 0u) << (2 * j + 1);
@@ -699,7 +718,7 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             err |= res < 0;
             if (nxt) {
                 s_nx[sh] = res;
-                if (res >= 0 && res == s_tw[sh]) push_tip(rc, tips, cap_tips, d, mi, 3 * base + sh, err);
+                if (res >= 0 && res == s_tw[sh]) tile_tip(s_tip, &s_ntip, tcap, sh, base, rc, tips, cap_tips, d, mi, err);
             } else {
                 s_pv[sh] = res;
             }
@@ -716,7 +735,8 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             err |= r < 0;
             if ((k & 1) == 0) {
                 s_nx[src[k]] = res;
-                if (res >= 0 && res == s_tw[src[k]]) push_tip(rc, tips, cap_tips, d, mi, 3 * base + src[k], err);
+                if (res >= 0 && res == s_tw[src[k]])
+                    tile_tip(s_tip, &s_ntip, tcap, src[k], base, rc, tips, cap_tips, d, mi, err);
             } else {
                 s_pv[src[k]] = res;
             }
@@ -724,6 +744,21 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
         }
     }
     __syncthreads();
+    if (tid == 0) {   // the tile's tips: one append
+        const int n = min(s_ntip, tcap);
+        if (n > 0) {
+            const int at = atomicAdd(&rc->ntips, n);
+            atomicAdd(&d.ctr->ntips, n);
+            for (int i = 0; i < n; i++) {
+                if (at + i < cap_tips) {
+                    tips[at + i].mesh = mi;
+                    tips[at + i].he = 3 * base + s_tip[i];
+                } else {
+                    err = true;
+                }
+            }
+        }
+    }
     if (cnt > 0) {
         store_from_lds((gint)(d.next_o) + 3 * (size_t)base, s_nx, 3 * cnt);
         store_from_lds((gint)(d.prev_o) + 3 * (size_t)base, s_pv, 3 * cnt);
@@ -745,56 +780,96 @@ __device__ __forceinline__ uint32_t set_frontier_bit(uint8_t *tflag, int h) {
     return atomicOr(word, bit) & bit;
 }
 
+// Appends 2 entries per lane with pred set; one atomic per wave.  Must be
+// reached by every lane of the wave.
+__device__ __forceinline__ int wave_reserve2(int32_t *counter, bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return -1;
+    const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, 2 * __popcll(mask));
+    base = __shfl(base, leader);
+    return pred ? base + 2 * __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+}
+
+// Middle edge of every barrier tip.  Whole waves take consecutive tips, so the
+// list appends and counters cost one atomic per wave (tips are many on
+// general-position meshes, and atomics on one address serialize).
 __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *tips,
                          int cap_tips, ListEntry *walk, int32_t *walk_counts, int walk_cap, ListEntry *fixes,
                          int cap_fix) {
     const int ntips = min(rc->ntips, cap_tips);
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ntips; k += gridDim.x * blockDim.x) {
-        const ListEntry e = tips[k];
-        const MeshDesc &d = descs[e.mesh];
-        const int32_t *__restrict__ twin = d.twin;
-        // a: the only frontier edge at the tip v = target(e.he), leaving v
-        const int a = twin[e.he];
-        bool err = a < 0;
-        int deg = 0, r = a;
-        while (!err) {   // degree: a full clockwise turn around v
-            int g = twin[r];
-            if (g < 0 || ++deg > kRotGuard) {
-                err = true;
-                break;
+    const int lane = __lane_id();
+    const int stride = gridDim.x * blockDim.x;
+    for (int wbase = blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)); wbase < ntips; wbase += stride) {
+        const int k = wbase + lane;
+        bool ok = k < ntips;
+        int mesh = 0, a = -1, m = -1, mt = -1;
+        bool newmid = false;
+        if (ok) {
+            const ListEntry e = tips[k];
+            mesh = e.mesh;
+            const MeshDesc &d = descs[e.mesh];
+            const gcint twin = (gcint)d.twin;
+            // a: the only frontier edge at the tip v = target(e.he), leaving v
+            a = twin[e.he];
+            bool err = a < 0;
+            int deg = 0, r = a;
+            while (!err) {   // degree: a full clockwise turn around v
+                const int g = twin[r];
+                if (g < 0 || ++deg > kRotGuard) {
+                    err = true;
+                    break;
+                }
+                r = he_next(g);
+                if (r == a) break;
             }
-            r = he_next(g);
-            if (r == a) break;
+            if (!err) {
+                m = a;
+                for (int s2 = 0; s2 < deg / 2; s2++) m = he_next(twin[m]);
+                mt = twin[m];
+                err = mt < 0;
+            }
+            if (err) {
+                atomicOr(&d.ctr->err, kErrCorrupt);
+                ok = false;
+            } else {
+                newmid = !set_frontier_bit(d.tflag, m < mt ? m : mt);
+                set_frontier_bit(d.tflag, m < mt ? mt : m);
+            }
         }
-        if (err) {
-            atomicOr(&d.ctr->err, kErrCorrupt);
-            continue;
-        }
-        int m = a;
-        for (int s = 0; s < deg / 2; s++) m = he_next(twin[m]);
-        const int mt = twin[m];
-        uint32_t had_lo = set_frontier_bit(d.tflag, m < mt ? m : mt);
-        set_frontier_bit(d.tflag, m < mt ? mt : m);
-        if (!had_lo) atomicAdd(&d.ctr->nmiddle, 1);
         // both halves of the middle edge seed the polygons on either side
-        const int stripe = k % kStripes;
-        const int c = atomicAdd(&walk_counts[stripe * kStripePad], 2);
-        if (c + 1 < walk_cap) {
-            walk[stripe * walk_cap + c].mesh = e.mesh;
-            walk[stripe * walk_cap + c].he = m;
-            walk[stripe * walk_cap + c + 1].mesh = e.mesh;
-            walk[stripe * walk_cap + c + 1].he = mt;
-        } else {
-            atomicOr(&d.ctr->err, kErrCorrupt);
+        const int stripe = (wbase / kWave) % kStripes;
+        const int c = wave_reserve2(&walk_counts[stripe * kStripePad], ok);
+        const int f = wave_reserve2(&rc->nfix, ok);
+        if (ok) {
+            bool full = false;
+            if (c + 1 < walk_cap) {
+                walk[stripe * walk_cap + c].mesh = mesh;
+                walk[stripe * walk_cap + c].he = m;
+                walk[stripe * walk_cap + c + 1].mesh = mesh;
+                walk[stripe * walk_cap + c + 1].he = mt;
+            } else {
+                full = true;
+            }
+            if (f + 1 < cap_fix) {
+                fixes[f].mesh = mesh;
+                fixes[f].he = a;        // leaves the tip
+                fixes[f + 1].mesh = mesh;
+                fixes[f + 1].he = mt;   // leaves the other end of the middle edge
+            } else {
+                full = true;
+            }
+            if (full) atomicOr(&descs[mesh].ctr->err, kErrCorrupt);
         }
-        int f = atomicAdd(&rc->nfix, 2);
-        if (f + 1 < cap_fix) {
-            fixes[f].mesh = e.mesh;
-            fixes[f].he = a;        // leaves the tip
-            fixes[f + 1].mesh = e.mesh;
-            fixes[f + 1].he = mt;   // leaves the other end of the middle edge
-        } else {
-            atomicOr(&d.ctr->err, kErrCorrupt);
+        // new middle edges, counted per mesh: one atomic per mesh in the wave
+        unsigned long long pending = __ballot(ok && newmid);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int lm = __shfl(mesh, leader);
+            const unsigned long long same = __ballot(ok && newmid && mesh == lm);
+            if (lane == leader) atomicAdd(&descs[lm].ctr->nmiddle, __popcll(same));
+            pending &= ~same;
         }
     }
 }
@@ -1373,7 +1448,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
 
     H(K_RELINK, 0);
     GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                    (sizeof(int) * 9 + 2 + 4) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
+                    (sizeof(int) * 9 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
                     rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, rb.status, cmp_tb);
     H(K_RELINK, 1);
 

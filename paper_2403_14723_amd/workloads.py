@@ -11,8 +11,10 @@ drawn before it.
 The workloads follow the shape of the paper's Grid meshes (Section 7.1,
 Algorithm 15: a square grid of points, each cell split into two triangles) at
 sizes comparable to its Table 1 / appendix rows.  Its Random (Delaunay) meshes
-need an external Delaunay code that is not available; jitter, random diagonals
-and a smooth warp stand in for the irregularity they bring.
+came from an external Delaunay code that is not available: jitter, random
+diagonals and a smooth warp bring irregularity to the grids, and
+random_delaunay (scipy's Qhull on seeded random points) stands in for the
+Random meshes themselves.
 
 Recipe (all coordinates are integers in [0, 2**20]):
   * n x n cells of side c = floor(2**20 / n); vertex (i, j) has id j*(n+1)+i and
@@ -181,13 +183,29 @@ def plain_large_warped() -> Mesh:
     return jittered_grid(4096, seed=2, warp=True, name="plain_4096x4096_warped")
 
 
-def random_delaunay(npts: int, seed: int, snap_frac: float = 1.0 / 200, name: str = "") -> Mesh:
+def _morton(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Interleaved bits of two 21-bit coordinates (Z-order key)."""
+    def spread(v):
+        v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+        v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+        v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+        return v
+    return spread(x) | (spread(y) << np.uint64(1))
+
+
+def random_delaunay(npts: int, seed: int, snap_frac: float = 1.0 / 200, name: str = "",
+                    order: str = "qhull") -> Mesh:
     """Delaunay triangulation of random integer points, after the paper's
     Random meshes (Section 7.1): points uniform in the square, points closer
     than delta = snap_frac * 2**20 to a side are moved onto that side, the four
     corners are added, duplicates are dropped.  The triangulation itself comes
     from scipy's Qhull binding (a stand-in for the Triangle code the paper
-    used)."""
+    used).  order="qhull" keeps Qhull's vertex and triangle numbering (nearly
+    random in space); order="morton" renumbers both along a Z-order curve, as
+    the output of a divide-and-conquer mesh generator is spatially coherent."""
     from scipy.spatial import Delaunay
 
     idx = np.arange(npts, dtype=np.uint64)
@@ -200,8 +218,18 @@ def random_delaunay(npts: int, seed: int, snap_frac: float = 1.0 / 200, name: st
                           np.stack([x, y], -1)])
     pts = np.unique(pts, axis=0)
     tri = Delaunay(pts).simplices
+    if order == "morton":
+        vkey = np.argsort(_morton(pts[:, 0], pts[:, 1]), kind="stable")
+        rank = np.empty_like(vkey)
+        rank[vkey] = np.arange(len(vkey))
+        pts = pts[vkey]
+        tri = rank[tri]
+        c = pts[tri].sum(axis=1) // 3
+        tri = tri[np.argsort(_morton(c[:, 0], c[:, 1]), kind="stable")]
+    elif order != "qhull":
+        raise ValueError(f"unknown order {order!r}")
     return Mesh(np.ascontiguousarray(pts.astype(np.int32)), np.ascontiguousarray(tri.astype(np.int32)),
-                name or f"delaunay{npts}_s{seed}")
+                name or f"delaunay{npts}_s{seed}" + ("m" if order == "morton" else ""))
 
 
 def _side_for(seed: int, stream: int, count: int, lo: float, hi: float) -> np.ndarray:

@@ -86,6 +86,7 @@ def _small_cases():
         out.append(W.jittered_grid(n, seed=7, jitter=0.0))
     for npts, seed in ((10, 1), (300, 2), (5000, 3), (60000, 4)):
         out.append(W.random_delaunay(npts, seed))
+    out.append(W.random_delaunay(60000, 9, order="morton"))   # spatially ordered numbering
     return out
 
 
