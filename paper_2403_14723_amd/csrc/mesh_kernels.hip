@@ -897,44 +897,90 @@ __device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
     return ok;
 }
 
+// Every fix-up anchor o (a half-edge leaving vertex x) gets a group of 32
+// lanes: lane j < 16 takes the outgoing half-edge j clockwise steps from o,
+// lane 16 + k the one k + 1 counter-clockwise steps away (only when the
+// clockwise turn met the boundary, i.e. x is on it), and each lane fixes
+// next'/prev' at its half-edge, so the turns around x run side by side.  The
+// last lane of each side continues past 16 steps on its own.
 __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *fixes,
                         int cap_fix) {
     const int nfix = min(rc->nfix, cap_fix);
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nfix; k += gridDim.x * blockDim.x) {
-        const ListEntry en = fixes[k];
+    const int lane = __lane_id(), gl = lane & 31;
+    const unsigned long long gmask = (lane < 32) ? 0x00000000ffffffffull : 0xffffffff00000000ull;
+    const unsigned long long cwmask = gmask & 0x0000ffff0000ffffull;   // lanes 0-15 of each group
+    const int groups = gridDim.x * (blockDim.x / 32);
+    for (int qb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 2; qb < nfix; qb += groups) {
+        const int q = qb + (lane >> 5);
+        const bool valid = q < nfix;
+        const ListEntry en = valid ? fixes[q] : ListEntry{0, 0};
         const MeshDesc &d = descs[en.mesh];
-        const int32_t *__restrict__ twin = d.twin;
+        const gcint twin = (gcint)d.twin;
         const int o = en.he;
-        bool ok = true, open = false;
-        int e = o, steps = 0;
-        do {   // clockwise over the outgoing half-edges
-            ok &= fix_around(d, e);
-            const int g = twin[e];
-            if (g < 0) {
-                open = true;
-                break;
-            }
-            e = he_next(g);
-            if (++steps > kRotGuard) {
-                ok = false;
-                break;
-            }
-        } while (e != o);
-        if (open && ok) {   // a boundary vertex: also go counter-clockwise
-            e = o;
-            steps = 0;
-            while (true) {
-                const int g = twin[he_prev(e)];
-                if (g < 0) break;
-                e = g;
-                ok &= fix_around(d, e);
-                if (++steps > kRotGuard) {
-                    ok = false;
+        bool ok = true, have = false, boundary = false;
+        int e = o;
+        if (valid && gl < 16) {   // clockwise: e <- next(twin(e)), gl steps
+            have = true;
+            for (int s2 = 0; s2 < gl; s2++) {
+                const int g = twin[e];
+                if (g < 0) {
+                    boundary = true;
+                    have = false;
+                    break;
+                }
+                e = he_next(g);
+                if (e == o) {   // around a closed fan in fewer steps: no edge of its own
+                    have = false;
                     break;
                 }
             }
         }
-        if (!ok) atomicOr(&d.ctr->err, kErrCorrupt);
+        // past 16 steps clockwise: the last lane goes on alone (and finds the
+        // boundary if the turn reaches it there)
+        if (have && gl == 15) {
+            int f = e;
+            for (int steps = 0;; steps++) {
+                const int g = twin[f];
+                if (g < 0) {
+                    boundary = true;
+                    break;
+                }
+                f = he_next(g);
+                if (f == o) break;
+                if (steps > kRotGuard) {
+                    ok = false;
+                    break;
+                }
+                ok &= fix_around(d, f);
+            }
+        }
+        const bool open = (__ballot(boundary) & cwmask & gmask) != 0ull;
+        if (valid && gl >= 16 && open) {   // counter-clockwise: e <- twin(prev(e)), gl - 15 steps
+            have = true;
+            for (int s2 = 0; s2 <= gl - 16; s2++) {
+                const int g = twin[he_prev(e)];
+                if (g < 0) {
+                    have = false;
+                    break;
+                }
+                e = g;
+            }
+        }
+        if (have) ok &= fix_around(d, e);
+        // past 16 steps counter-clockwise: the last lane goes on alone
+        if (have && gl == 31) {
+            for (int steps = 0;; steps++) {
+                const int g = twin[he_prev(e)];
+                if (g < 0) break;
+                e = g;
+                if (steps > kRotGuard) {
+                    ok = false;
+                    break;
+                }
+                ok &= fix_around(d, e);
+            }
+        }
+        if (valid && !ok) atomicOr(&d.ctr->err, kErrCorrupt);
     }
 }
 

@@ -276,3 +276,22 @@ def test_launch_specs_do_not_change_results(spec):
         c.set_launch(spec)
         g = run_gpu(c, m.xy, m.tri, f"{m.name} {spec}")
     assert_parity(g, o, spec)
+
+
+def _wheel(n):
+    """n triangles around one centre, radii growing around the rim: every spoke
+    but the first is the longest edge of a triangle, so the centre is a
+    barrier tip of degree n (fix-up turns around a vertex of any degree)."""
+    import math
+    c = 1 << 19
+    pts = [[c, c]] + [[int(c + 200000 * (1 + 0.3 * k / n) * math.cos(2 * math.pi * k / n)),
+                       int(c + 200000 * (1 + 0.3 * k / n) * math.sin(2 * math.pi * k / n))] for k in range(n)]
+    tri = [[0, 1 + k, 1 + (k + 1) % n] for k in range(n)]
+    return np.array(pts, np.int32), np.array(tri, np.int32)
+
+
+@pytest.mark.parametrize("n", [12, 20, 40, 64])
+def test_wheel_tip_of_high_degree(ctx, n):
+    xy, tri = _wheel(n)
+    g, o = check_case(ctx, xy, tri, f"wheel{n}")
+    assert o.stats["ntips"] == 1
