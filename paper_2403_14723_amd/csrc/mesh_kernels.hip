@@ -252,11 +252,24 @@ __device__ __forceinline__ int striped_index(const int *s_pref, int cap, int g) 
 }
 
 // Copies n ints from global src to LDS dst; src and dst 16-byte aligned.
+// PER: 16-byte loads per thread that cover n (n <= 4 * PER * blockDim.x); all
+// of a thread's loads are issued before the first is used.
+template <int PER>
 __device__ __forceinline__ void load_to_lds(int *dst, gcint src, int n) {
-    const int B = blockDim.x, tid = threadIdx.x;
+    const int B = blockDim.x, tid = threadIdx.x, n4 = n / 4;
     GLOBAL const v4i *s4 = reinterpret_cast<GLOBAL const v4i *>(src);
     v4i *d4 = reinterpret_cast<v4i *>(dst);
-    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
+    v4i v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; p++) {
+        const int k = tid + p * B;
+        v[p] = s4[k < n4 ? k : 0];
+    }
+#pragma unroll
+    for (int p = 0; p < PER; p++) {
+        const int k = tid + p * B;
+        if (k < n4) d4[k] = v[p];
+    }
     for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
 }
 
@@ -314,23 +327,33 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
     // the tile's corners in one contiguous load; item j of this thread is
     // triangle base + j*B + tid
     const int cnt_all = min(B * ITEMS, nt - base);
-    if (cnt_all > 0) load_to_lds(s_org, (gcint)(d.org) + 3 * (size_t)base, 3 * cnt_all);
+    if (cnt_all <= 0) return;   // an empty mesh's tile (the whole block)
+    load_to_lds<(3 * ITEMS + 3) / 4>(s_org, (gcint)(d.org) + 3 * (size_t)base, 3 * cnt_all);
     __syncthreads();
+    // every corner of every item first, so all the gathers are in flight
+    // together (items past the tile read corner 0 and are dropped)
+    v2i q[ITEMS][3];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
+        const int l0 = lt < cnt_all ? 3 * lt : 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++) q[j][i] = xy[s_org[l0 + i]];
+    }
+    gu8 tflag = (gu8)d.tflag;
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt >= cnt_all) continue;
         const int t = base + lt;
-        if (t >= nt) break;
-        const v2i q0 = xy[s_org[3 * lt]], q1 = xy[s_org[3 * lt + 1]], q2 = xy[s_org[3 * lt + 2]];
-        const int2 p0 = make_int2(q0.x, q0.y), p1 = make_int2(q1.x, q1.y), p2 = make_int2(q2.x, q2.y);
+        const int2 p0 = make_int2(q[j][0].x, q[j][0].y), p1 = make_int2(q[j][1].x, q[j][1].y),
+                   p2 = make_int2(q[j][2].x, q[j][2].y);
         const long long l0 = sq_len(p0, p1), l1 = sq_len(p1, p2), l2 = sq_len(p2, p0);
         long long m = l0 > l1 ? l0 : l1;
         m = m > l2 ? m : l2;
         const int cnt = (l0 == m) + (l1 == m) + (l2 == m);
-        int best;
-        if (cnt == 1) {
-            best = l0 == m ? 0 : (l1 == m ? 1 : 2);
-        } else {
+        int best = l0 == m ? 0 : (l1 == m ? 1 : 2);
+        if (cnt > 1) {
             // tie at the maximum: the lower edge id min(h, twin h) wins
             best = -1;
             int bid = 0x7fffffff;
@@ -346,7 +369,7 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
             }
             atomicAdd(&d.ctr->nties, 1);
         }
-        ((gu8)d.tflag)[t] = (uint8_t)best;
+        tflag[t] = (uint8_t)best;
     }
 }
 
@@ -517,7 +540,7 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     const int base = (tile - d.he_tile0) * TB;
     const int cnt = min(TB, nt - base);
     if (cnt <= 0) return;   // an empty mesh's tile (the whole block)
-    load_to_lds(s_tw, twin + 3 * (size_t)base, 3 * cnt);
+    load_to_lds<(3 * ITEMS + 3) / 4>(s_tw, twin + 3 * (size_t)base, 3 * cnt);
     __syncthreads();
     // phase 1: labels of the triangle and its neighbours -> frontier, seed.
     // Every load is issued unconditionally (indices clamped to 0, results
