@@ -1350,17 +1350,19 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     const bool fits = tsum <= 3 * TB && pc + tcnt <= nt && ps + tsum <= nh;
     // 3. seeds, local offsets and loops; into LDS, or straight to global
     //    memory for a tile whose loops do not fit
-    int *he_out = fits ? s_he : d.loop_he + ps;
     // A loop of 3 is one triangle: (mn, next, prev).  A loop of 4 is two
     // triangles: the minimum's triangle has frontier half-edges a, b = next(a)
     // and crosses to the other triangle at b, whose two frontier half-edges
     // follow as p1 = next'(b), next(p1).  Longer loops get their offset here
     // and are written by k_emit.
-    int q = ecn & 0xffff, off = esum, e = (ecn >> 16);
     __syncthreads();
-    e += stripe * emit_cap + s_ebase;
     const int elim = (stripe + 1) * emit_cap;
     bad |= s_ebase + tnd > emit_cap;
+    // the body is instantiated twice: loops into LDS (the tile fits, the
+    // usual case), or straight to global memory; the tile decides for all
+    // its threads
+    auto place_loops = [&](auto he_out) {
+    int q = ecn & 0xffff, off = esum, e = (ecn >> 16) + stripe * emit_cap + s_ebase;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         if (!code[j]) continue;
@@ -1443,6 +1445,11 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         ++q;
         off += lens[j];
     }
+    };
+    if (fits)
+        place_loops(s_he);
+    else
+        place_loops((gint)d.loop_he + ps);
     if (fits) {
         __syncthreads();
         // contiguous stores of the tile's part of seeds, loop_off, loop_he
