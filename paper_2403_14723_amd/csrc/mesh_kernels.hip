@@ -51,6 +51,7 @@ typedef GLOBAL int32_t *gint;
 typedef GLOBAL const uint8_t *gcu8;
 typedef GLOBAL uint8_t *gu8;
 typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v3i __attribute__((ext_vector_type(3)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef GLOBAL const v2i *gcv2i;
 
@@ -522,8 +523,8 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     extern __shared__ int4 lds_raw[];
     int *lds = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x, TB = B * ITEMS;
-    int *s_tw = lds, *s_nx = lds + 3 * TB, *s_pv = lds + 6 * TB;
-    uint8_t *s_f = reinterpret_cast<uint8_t *>(lds + 9 * TB);   // label bytes
+    int *s_tw = lds;                                            // the tile's twins
+    uint8_t *s_f = reinterpret_cast<uint8_t *>(lds + 3 * TB);   // label bytes
     uint8_t *s_pl = s_f + TB;                                   // loop bytes
     int *s_q = reinterpret_cast<int *>(s_pl + TB);              // queued turns, 2 ints each
     const int qcap = TB / 2;
@@ -537,6 +538,7 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     const int nt = d.nt;
     const gcint twin = (gcint)(d.twin);
     const gu8 tflag = (gu8)(d.tflag);
+    const gint nxo = (gint)(d.next_o), pvo = (gint)(d.prev_o);
     const int base = (tile - d.he_tile0) * TB;
     const int cnt = min(TB, nt - base);
     if (cnt <= 0) return;   // an empty mesh's tile (the whole block)
@@ -596,6 +598,8 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     uint32_t pend = 0;  // bit 2j (2j+1): the next' (prev') turn of item j goes on
     int cur[2 * ITEMS], lab[2 * ITEMS], src[2 * ITEMS];   // turn state; src: the
                                                           // local index of the half-edge
+    int nv3[ITEMS][3], pv3[ITEMS][3];                     // this lane's next'/prev'
+    int qslot[2 * ITEMS];                                 // LDS queue slot of turn k, or -1
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;   // lt >= cnt: f[j] == 0, so nothing is queued
@@ -604,12 +608,12 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
         const uint32_t rn = ((F3 >> 1) | (F3 << 2)) & 7u;   // bit i: edge i+1 frontier
         const uint32_t rp = ((F3 << 1) | (F3 >> 2)) & 7u;   // bit i: edge i-1 frontier
         const uint32_t mn = F3 & ~rn, mp = F3 & ~rp;        // at most one bit each
-        // in-triangle values (the turn's slot is overwritten when it ends);
-        // entries past cnt are never stored
+        // in-triangle values (the turn's slot gets its value when the turn ends)
+        int nxv[3], pvv[3];
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            s_nx[3 * lt + i] = ((F3 & rn) >> i) & 1u ? h0 + (i == 2 ? 0 : i + 1) : -1;
-            s_pv[3 * lt + i] = ((F3 & rp) >> i) & 1u ? h0 + (i == 0 ? 2 : i - 1) : -1;
+            nxv[i] = ((F3 & rn) >> i) & 1u ? h0 + (i == 2 ? 0 : i + 1) : -1;
+            pvv[i] = ((F3 & rp) >> i) & 1u ? h0 + (i == 0 ? 2 : i - 1) : -1;
         }
         // next' turn: from the frontier half-edge na, across x = next(na)
         const int na = mn ? __builtin_ctz(mn) : 0, x = na == 2 ? 0 : na + 1;
@@ -634,13 +638,20 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
         const bool hitn = mn && inn && fbit(fbn, cn - 3 * tn);
         const bool hitq = mp && inq && fbit(fbq, cp - 3 * tq);
         if (hitn) {
-            s_nx[3 * lt + na] = cn;
             // next'(h) == twin(h): the target of h is a barrier tip
             if (cn == (na == 0 ? tw[j][0] : (na == 1 ? tw[j][1] : tw[j][2])))
                 tile_tip(s_tip, &s_ntip, tcap, 3 * lt + na, base, rc, tips, cap_tips, d, mi, err);
         }
-        if (hitq) s_pv[3 * lt + pa] = cp;
-        pend |= (mn && !hitn ? 1u : 0u) << (2 * j) | (mp && !hitq ? 1u : 0u) << (2 * j + 1);
+        const bool pn = mn && !hitn, pp = mp && !hitq;   // turns that go on
+        pend |= (pn ? 1u : 0u) << (2 * j) | (pp ? 1u : 0u) << (2 * j + 1);
+        // this triangle's next'/prev' stay in registers until the tile is done
+        // (a turn that goes on fills its slot later), then go out as one
+        // 12-byte store each, so every line is written once and whole
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            nv3[j][i] = (mn && i == na) ? cn : nxv[i];
+            pv3[j][i] = (mp && i == pa) ? cp : pvv[i];
+        }
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
@@ -709,10 +720,12 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
         }
 #pragma unroll
         for (int k = 0; k < 2 * ITEMS; k++) {
+            qslot[k] = -1;
             if (!((pend >> k) & 1u)) continue;
             if (eq < qcap) {
                 s_q[2 * eq] = cur[k];
                 s_q[2 * eq + 1] = (src[k] << 3) | ((k & 1) == 0 ? 4 : 0) | (lab[k] + 1);
+                qslot[k] = eq;
                 pend &= ~(1u << k);
             }
             ++eq;
@@ -739,12 +752,9 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             const bool nxt = (w & 4) != 0;
             const int res = run_turn(T, s_q[2 * q], (w & 3) - 1, nxt);
             err |= res < 0;
-            if (nxt) {
-                s_nx[sh] = res;
-                if (res >= 0 && res == s_tw[sh]) tile_tip(s_tip, &s_ntip, tcap, sh, base, rc, tips, cap_tips, d, mi, err);
-            } else {
-                s_pv[sh] = res;
-            }
+            s_q[2 * q] = res;   // the owner picks it up after the barrier
+            if (nxt && res >= 0 && res == s_tw[sh])
+                tile_tip(s_tip, &s_ntip, tcap, sh, base, rc, tips, cap_tips, d, mi, err);
         }
     }
     // turns beyond the queue (meshes whose polygons are mostly large), in registers
@@ -756,17 +766,49 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
             if (r == 0) continue;
             const int res = r > 0 ? cur[k] : -1;
             err |= r < 0;
+            const int li = src[k] % 3;
             if ((k & 1) == 0) {
-                s_nx[src[k]] = res;
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    if (i == li) nv3[k >> 1][i] = res;
                 if (res >= 0 && res == s_tw[src[k]])
                     tile_tip(s_tip, &s_ntip, tcap, src[k], base, rc, tips, cap_tips, d, mi, err);
             } else {
-                s_pv[src[k]] = res;
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    if (i == li) pv3[k >> 1][i] = res;
             }
             pend &= ~(1u << k);
         }
     }
     __syncthreads();
+    // next'/prev' of this lane's triangles, with the queued turns' results
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt >= cnt) continue;
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++) {
+            const int k = 2 * j + kk;
+            if (qslot[k] < 0) continue;
+            const int res = s_q[2 * qslot[k]], li = src[k] - 3 * lt;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                if (i != li) continue;
+                if (kk == 0)
+                    nv3[j][i] = res;
+                else
+                    pv3[j][i] = res;
+            }
+        }
+        const int h0 = 3 * (base + lt);
+        *reinterpret_cast<GLOBAL v3i *>(nxo + h0) = v3i{nv3[j][0], nv3[j][1], nv3[j][2]};
+        *reinterpret_cast<GLOBAL v3i *>(pvo + h0) = v3i{pv3[j][0], pv3[j][1], pv3[j][2]};
+    }
+    // the tile's label and loop bytes in whole words (the label bytes keep
+    // their longest-edge bits, which other tiles may be reading)
+    store_bytes_from_lds((gu8)(d.pl) + base, s_pl, cnt);
+    store_bytes_from_lds(tflag + base, s_f, cnt);
     if (tid == 0) {   // the tile's tips: one append
         const int n = min(s_ntip, tcap);
         if (n > 0) {
@@ -781,12 +823,6 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
                 }
             }
         }
-    }
-    if (cnt > 0) {
-        store_from_lds((gint)(d.next_o) + 3 * (size_t)base, s_nx, 3 * cnt);
-        store_from_lds((gint)(d.prev_o) + 3 * (size_t)base, s_pv, 3 * cnt);
-        store_bytes_from_lds((gu8)(d.pl) + base, s_pl, cnt);
-        store_bytes_from_lds(tflag + base, s_f, cnt);
     }
     if (err) atomicOr(&d.ctr->err, kErrCorrupt);
 }
@@ -1524,7 +1560,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
 
     H(K_RELINK, 0);
     GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                    (sizeof(int) * 9 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
+                    (sizeof(int) * 3 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
                     rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, rb.status, cmp_tb);
     H(K_RELINK, 1);
 
