@@ -139,6 +139,64 @@ def bench_batched(gp, W, stream, steps):
     return out
 
 
+def bench_transfers(gp, W, stream, reps=5):
+    """With-transfer rates of the two smaller plain configurations (the large
+    one is measured in main): H2D of xy and tri from pinned host memory, the
+    half-edge build, one meshing run (graph replay) and D2H of every output
+    into pinned host memory, each timed with HIP events; medians of reps."""
+    import numpy as np
+    import torch
+    out = {}
+    ctx = gp.Context(0, stream=stream.cuda_stream)
+    dev = torch.device("cuda:0")
+    for mesh in (W.plain_small(), W.plain_scale()):
+        xy_h = torch.from_numpy(mesh.xy).pin_memory()
+        tri_h = torch.from_numpy(mesh.tri).pin_memory()
+        rows = []
+        for _ in range(reps + 1):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(stream)
+            xy_d = xy_h.to(dev, non_blocking=True)
+            tri_d = tri_h.to(dev, non_blocking=True)
+            ev[1].record(stream)
+            h = ctx.build_halfedges(xy_d, tri_d)
+            ev[2].record(stream)
+            r = ctx.mesh(h)   # synchronous: the output sizes are needed for the copy
+            info = r.info()
+            bufs = [torch.empty(max(n, 1), dtype=torch.int32).pin_memory()
+                    for n in (info["nh"], info["nh"], info["npoly"], info["npoly"] + 1, info["nloop_he"])]
+            torch.cuda.synchronize()
+            ev[3].record(stream)
+            rc = gp.library().gpolylla_result_copy(r.handle, *[b.data_ptr() for b in bufs])
+            ev[4].record(stream)
+            torch.cuda.synchronize()
+            assert rc == gp.GP_OK, rc
+            rows.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[3].elapsed_time(ev[4])])
+            r.free()
+            h.free()
+        h2d, build, d2h = np.median(np.array(rows[1:]), axis=0)
+        # the device time of one meshing run, from graph replays
+        h = ctx.build_halfedges(xy_h.numpy(), tri_h.numpy())
+        for _ in range(3):
+            ctx.mesh(h, gp.GP_ASYNC | gp.GP_GRAPH).free()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(20):
+            ctx.mesh(h, gp.GP_ASYNC | gp.GP_GRAPH).free()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dev_ms = e0.elapsed_time(e1) / 20
+        h.free()
+        total = h2d + build + dev_ms + d2h
+        out[mesh.name] = {"triangles": mesh.nt, "h2d_ms": round(float(h2d), 4), "build_ms": round(float(build), 4),
+                          "mesh_ms": round(float(dev_ms), 4), "d2h_ms": round(float(d2h), 4),
+                          "device_mtri_s": round(mesh.nt / (dev_ms * 1e-3) / 1e6, 1),
+                          "with_copies_mtri_s": round(mesh.nt / (total * 1e-3) / 1e6, 1)}
+    ctx.close()
+    return out
+
+
 def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
     """The general-position workload (the paper's Random meshes): a Delaunay
     triangulation of random points, numbered along a Z-order curve, meshed on
@@ -361,8 +419,11 @@ def main():
     value = nt / (ms_per_step * 1e-3) / 1e6
     traffic, traffic_src = measured_traffic(dom.split("<")[0])
 
-    batched = served = delaunay = None
+    batched = served = delaunay = transfers = None
     if not args.no_forms:
+        log("[bench] transfers of the smaller plain configurations")
+        transfers = bench_transfers(gp, W, stream)
+        log(f"[bench] {transfers}")
         log("[bench] general-position workload (Delaunay, 1M points)")
         delaunay = bench_delaunay(gp, W, stream, max(5, args.steps // 2))
         log(f"[bench] {delaunay}")
@@ -405,6 +466,7 @@ def main():
         "batched": batched,
         "served": served,
         "delaunay": delaunay,
+        "transfers": transfers,
         "cpu_baseline": cpu,
     }
     if check is not None:

@@ -115,19 +115,6 @@ __device__ __forceinline__ int turn_prev(const int32_t *__restrict__ twin, const
 // wave / block helpers
 // ---------------------------------------------------------------------------
 
-// Appends one entry per lane with pred set; one atomic per wave.  Must be
-// reached by every active lane of the wave.
-__device__ __forceinline__ int wave_reserve(int32_t *counter, bool pred) {
-    unsigned long long mask = __ballot(pred);
-    if (mask == 0ull) return -1;
-    int lane = __lane_id();
-    int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader);
-    return pred ? base + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
-}
-
 __device__ __forceinline__ void wave_incl_scan2(int &a, int &b) {
     int lane = __lane_id();
 #pragma unroll
@@ -138,12 +125,6 @@ __device__ __forceinline__ void wave_incl_scan2(int &a, int &b) {
             b += tb;
         }
     }
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
 }
 
 // Exclusive block scan of a pair; lds must hold 66 ints.
@@ -203,22 +184,6 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * q + (x < r ? x : r) + k;
 }
 
-// Block-wide reservation in stripe `stripe` of a striped list: every thread
-// asks for n entries; one atomic per block.  Returns the thread's first entry
-// index (stripe*cap + slot); slots at or beyond cap are dropped by the caller
-// and reported through *full.  Called by every thread of the block.
-__device__ __forceinline__ int block_reserve(int32_t *counts, int cap, int stripe, int n, int *s_scan,
-                                             int *s_base, bool *full) {
-    int excl, dummy, total, dummy2;
-    block_excl_scan2(n, 0, excl, dummy, total, dummy2, s_scan);
-    if (threadIdx.x == 0) *s_base = total > 0 ? atomicAdd(&counts[stripe * kStripePad], total) : 0;
-    __syncthreads();
-    const int base = *s_base;
-    __syncthreads();
-    if (base + total > cap) *full = true;
-    return stripe * cap + base + excl;
-}
-
 // Prefix sums of the stripe sizes in LDS (s_pref[0..kStripes]); returns the
 // total.  Called by every thread of the block.
 __device__ __forceinline__ int striped_prefix(const int32_t *counts, int cap, int *s_pref) {
@@ -271,15 +236,6 @@ __device__ __forceinline__ void load_to_lds(int *dst, gcint src, int n) {
         const int k = tid + p * B;
         if (k < n4) d4[k] = v[p];
     }
-    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
-}
-
-// Copies n ints from LDS src to global dst; both 16-byte aligned.
-__device__ __forceinline__ void store_from_lds(gint dst, const int *src, int n) {
-    const int B = blockDim.x, tid = threadIdx.x;
-    const v4i *s4 = reinterpret_cast<const v4i *>(src);
-    GLOBAL v4i *d4 = reinterpret_cast<GLOBAL v4i *>(dst);
-    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
     for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
 }
 
