@@ -124,7 +124,7 @@ struct RunBuffers {
 // k_walk records each chain's half-edges in LDS, up to this many; longer
 // loops are left to k_emit
 constexpr int kWalkBuf = 16;
-constexpr int kWalkItems = 2;   // chains per k_walk thread
+constexpr int kWalkItems = 1;   // chains per k_walk thread
 constexpr int kScanChunk = 1024;   // compaction tiles per k_tile_scan block
 
 enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
