@@ -115,16 +115,40 @@ __device__ __forceinline__ int turn_prev(const int32_t *__restrict__ twin, const
 // wave / block helpers
 // ---------------------------------------------------------------------------
 
+// v read from the lane that DPP control CTRL names, in the rows ROW_MASK
+// selects; 0 where there is no such lane or the row is not selected
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_or_zero(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive scans over the 64 lanes of a wave; every lane must be active.
+// Lanes form four rows of 16: shifts right by 1, 2, 4 and 8 lanes within each
+// row scan the rows, then lane 15's total is added to row 1 and row 3, and
+// lane 31's (rows 0-1) to rows 2 and 3.  One DPP add per step, no LDS.
 __device__ __forceinline__ void wave_incl_scan2(int &a, int &b) {
-    int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int ta = __shfl_up(a, d), tb = __shfl_up(b, d);
-        if (lane >= d) {
-            a += ta;
-            b += tb;
-        }
-    }
+    a += dpp_or_zero<0x111, 0xf>(a);   // row_shr:1
+    b += dpp_or_zero<0x111, 0xf>(b);
+    a += dpp_or_zero<0x112, 0xf>(a);   // row_shr:2
+    b += dpp_or_zero<0x112, 0xf>(b);
+    a += dpp_or_zero<0x114, 0xf>(a);   // row_shr:4
+    b += dpp_or_zero<0x114, 0xf>(b);
+    a += dpp_or_zero<0x118, 0xf>(a);   // row_shr:8
+    b += dpp_or_zero<0x118, 0xf>(b);
+    a += dpp_or_zero<0x142, 0xa>(a);   // row_bcast:15 into rows 1, 3
+    b += dpp_or_zero<0x142, 0xa>(b);
+    a += dpp_or_zero<0x143, 0xc>(a);   // row_bcast:31 into rows 2, 3
+    b += dpp_or_zero<0x143, 0xc>(b);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int a) {
+    a += dpp_or_zero<0x111, 0xf>(a);
+    a += dpp_or_zero<0x112, 0xf>(a);
+    a += dpp_or_zero<0x114, 0xf>(a);
+    a += dpp_or_zero<0x118, 0xf>(a);
+    a += dpp_or_zero<0x142, 0xa>(a);
+    a += dpp_or_zero<0x143, 0xc>(a);
+    return a;
 }
 
 // Exclusive block scan of a pair; lds must hold 66 ints.
@@ -1098,16 +1122,11 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
             int mine = 0;
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) mine += need[j];
-            int incl = mine;
-#pragma unroll
-            for (int dd = 1; dd < kWave; dd <<= 1) {
-                const int y = __shfl_up(incl, dd);
-                if (lane >= dd) incl += y;
-            }
-            const int wtot = __shfl(incl, kWave - 1);
+            const int incl = wave_incl_scan(mine);   // the loop's exit is wave-uniform: all lanes here
+            const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
             int wbase = 0;
             if (lane == 0 && wtot > 0) wbase = atomicAdd(&wbuf_counts[wstripe * kStripePad], wtot);
-            wbase = __shfl(wbase, 0);
+            wbase = __builtin_amdgcn_readlane(wbase, 0);
             if (mine > 0 && wbase + wtot <= wbuf_cap) {
                 int pos = wstripe * wbuf_cap + wbase + incl - mine;
 #pragma unroll
