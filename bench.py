@@ -197,14 +197,10 @@ def bench_transfers(gp, W, stream, reps=5):
     return out
 
 
-def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
-    """The general-position workload (the paper's Random meshes): a Delaunay
-    triangulation of random points, numbered along a Z-order curve, meshed on
-    the device like the plain workload (graph replay)."""
+def _graph_form(gp, stream, m, steps):
+    """Graph-replay time of the meshing chain on mesh m (inputs resident),
+    its counts, and per-kernel times from a profiled pass."""
     import torch
-    t0 = time.perf_counter()
-    m = W.random_delaunay(npts, seed=21, order="morton")
-    gen_s = time.perf_counter() - t0
     ctx = gp.Context(0, stream=stream.cuda_stream)
     h = ctx.build_halfedges(m.xy, m.tri)
     flags = gp.GP_ASYNC | gp.GP_GRAPH
@@ -234,7 +230,31 @@ def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
     ctx.close()
     return {"workload": m.name, "triangles": m.nt, "vertices": m.nv, "polygons": info["npoly"],
             "loop_half_edges": info["nloop_he"], "tips": info["ntips"], "ms_per_step": round(ms, 4),
-            "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms, "generate_s": round(gen_s, 1)}
+            "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms}
+
+
+def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
+    """The general-position workload (the paper's Random meshes): a Delaunay
+    triangulation of random points, numbered along a Z-order curve, meshed on
+    the device like the plain workload (graph replay)."""
+    t0 = time.perf_counter()
+    m = W.random_delaunay(npts, seed=21, order="morton")
+    gen_s = time.perf_counter() - t0
+    out = _graph_form(gp, stream, m, steps)
+    out["generate_s"] = round(gen_s, 1)
+    return out
+
+
+def bench_band(gp, W, stream, mesh, steps, nbands=8, band=3):
+    """One device's share when the headline grid is split into nbands row
+    bands: band `band` with its two halo rows, meshed on its own (graph
+    replay).  Only for an n x n grid workload; None otherwise."""
+    n = int(round((mesh.nt // 2) ** 0.5))
+    if 2 * n * n != mesh.nt or (n + 1) ** 2 != mesh.nv or n % nbands:
+        return None
+    out = _graph_form(gp, stream, W.grid_band(mesh, n, band, nbands), steps)
+    out["band_proper_triangles"] = 2 * n * (n // nbands)
+    return out
 
 
 def bench_served(gp, W, n_req=2000, warm=64, cap_n=256, rhos=(0.5, 0.8)):
@@ -419,8 +439,11 @@ def main():
     value = nt / (ms_per_step * 1e-3) / 1e6
     traffic, traffic_src = measured_traffic(dom.split("<")[0])
 
-    batched = served = delaunay = transfers = None
+    batched = served = delaunay = transfers = band = None
     if not args.no_forms:
+        log("[bench] one row band of an 8-way split (two halo rows)")
+        band = bench_band(gp, W, stream, mesh, max(5, args.steps // 2))
+        log(f"[bench] {band}")
         log("[bench] transfers of the smaller plain configurations")
         transfers = bench_transfers(gp, W, stream)
         log(f"[bench] {transfers}")
@@ -466,6 +489,7 @@ def main():
         "batched": batched,
         "served": served,
         "delaunay": delaunay,
+        "band": band,
         "transfers": transfers,
         "cpu_baseline": cpu,
     }

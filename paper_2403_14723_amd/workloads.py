@@ -164,6 +164,28 @@ def jittered_grid(n: int, seed: int, jitter: float = 0.2, warp: bool = False,
     return Mesh(xy, grid_triangles(n, diag), name or f"grid{n}{'w' if warp else ''}_s{seed}")
 
 
+def grid_band(m: Mesh, n: int, band: int, nbands: int, halo: int = 2) -> Mesh:
+    """Cell rows [band*n/nbands - halo, (band+1)*n/nbands + halo) of an n x n
+    grid mesh made by jittered_grid, clipped to the grid, as a mesh of its own
+    (vertices renumbered in their original order).  This is one device's share
+    when a large grid is split into row bands.  On the grid, each halo row is
+    one vertex ring around the band; two rings keep the repaired frontier and
+    next'/prev' of every half-edge of the band proper equal to those of the
+    whole mesh (a barrier tip on the outer ring can add a middle edge that
+    ends on the inner one)."""
+    if n % nbands or not (0 <= band < nbands) or halo < 0 or m.nt != 2 * n * n:
+        raise ValueError("band of a whole n x n grid mesh, n divisible by nbands")
+    rows = n // nbands
+    j0 = max(0, band * rows - halo)
+    j1 = min(n, (band + 1) * rows + halo)
+    tri = m.tri[2 * n * j0:2 * n * j1]
+    # the band's vertices are the rows j0..j1 of the (n+1)-wide vertex grid
+    v0 = j0 * (n + 1)
+    xy = m.xy[v0:(j1 + 1) * (n + 1)]
+    return Mesh(np.ascontiguousarray(xy), np.ascontiguousarray(tri - v0),
+                f"{m.name or 'grid'}_band{band}of{nbands}")
+
+
 # ---------------------------------------------------------------------------
 # The five workloads
 # ---------------------------------------------------------------------------

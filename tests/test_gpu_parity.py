@@ -295,3 +295,21 @@ def test_wheel_tip_of_high_degree(ctx, n):
     xy, tri = _wheel(n)
     g, o = check_case(ctx, xy, tri, f"wheel{n}")
     assert o.stats["ntips"] == 1
+
+
+def test_grid_bands(ctx):
+    """One device's share of a row-band split with two halo rows: every band
+    meshes like any mesh, and the half-edges of its band proper get the whole
+    grid's next'/prev' (shifted by the cut)."""
+    n, nb = 256, 8
+    m = W.jittered_grid(n, seed=41, warp=True)
+    whole, _ = check_case(ctx, m.xy, m.tri, m.name)
+    rows = n // nb
+    for b in range(nb):
+        bm = W.grid_band(m, n, b, nb)
+        g, _ = check_case(ctx, bm.xy, bm.tri, bm.name)
+        off = 6 * n * max(0, b * rows - 2)
+        lo, hi = 6 * n * b * rows - off, 6 * n * (b + 1) * rows - off
+        for key in ("next", "prev"):
+            got = g[key][lo:hi]
+            np.testing.assert_array_equal(np.where(got >= 0, got + off, -1), whole[key][lo + off:hi + off])
