@@ -52,6 +52,8 @@ typedef GLOBAL const uint8_t *gcu8;
 typedef GLOBAL uint8_t *gu8;
 typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v3i __attribute__((ext_vector_type(3)));
+// three ints at 4-byte alignment (a v3i claims 16): loads of 12-byte records
+typedef int v3i_a4 __attribute__((ext_vector_type(3), aligned(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef GLOBAL const v2i *gcv2i;
 
@@ -496,7 +498,7 @@ __device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc)
 }
 
 template <int ITEMS>
-__global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
                                                   RunCounters *rc, ListEntry *tips, int cap_tips,
                                                   ListEntry *walk, int32_t *walk_counts, int walk_cap,
                                                   uint64_t *agg, int cmp_tb) {
@@ -522,25 +524,34 @@ __global__ void __launch_bounds__(1024) k_relink(const MeshDesc *__restrict__ de
     const int base = (tile - d.he_tile0) * TB;
     const int cnt = min(TB, nt - base);
     if (cnt <= 0) return;   // an empty mesh's tile (the whole block)
-    load_to_lds<(3 * ITEMS + 3) / 4>(s_tw, twin + 3 * (size_t)base, 3 * cnt);
-    __syncthreads();
     // phase 1: labels of the triangle and its neighbours -> frontier, seed.
-    // Every load is issued unconditionally (indices clamped to 0, results
-    // masked after) so that all of them are in flight together.
+    // Each thread loads its triangles' twins itself (12 contiguous bytes per
+    // triangle, so a wave's loads are contiguous) and issues the label
+    // gathers as soon as they arrive; the twins go to LDS for the turns of
+    // phase 2, published by the barrier after the label bytes.  Every load is
+    // issued unconditionally (indices clamped to 0, results masked after) so
+    // that all of them are in flight together.
     int tw[ITEMS][3];
     uint32_t f[ITEMS], fn[ITEMS][3];
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
         const bool ok = lt < cnt;
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            const int g = s_tw[3 * lt + i];   // within the LDS tile; masked below
-            tw[j][i] = ok ? g : -1;
-        }
+        const v3i_a4 g = *(GLOBAL const v3i_a4 *)(twin + 3 * (size_t)(base + (ok ? lt : 0)));
+        tw[j][0] = ok ? g.x : -1;
+        tw[j][1] = ok ? g.y : -1;
+        tw[j][2] = ok ? g.z : -1;
         f[j] = tflag[base + (ok ? lt : 0)];
 #pragma unroll
         for (int i = 0; i < 3; i++) fn[j][i] = tflag[tri_of(tw[j][i] < 0 ? 0 : tw[j][i])];
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt < cnt) {
+#pragma unroll
+            for (int i = 0; i < 3; i++) s_tw[3 * lt + i] = tw[j][i];
+        }
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
