@@ -366,9 +366,10 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
 // frontier half-edge (Section 6.5): a candidate in the tile reads its
 // frontier bit from LDS; one outside derives it from the longest-edge labels,
 // which no kernel changes during this pass (the tile's label bytes are
-// written back with their longest-edge bits unchanged).  Twins, next/prev and
-// the label and loop bytes move through LDS, so global accesses are
-// contiguous.
+// written back with their longest-edge bits unchanged).  Each thread loads
+// its triangles' twins and stores their next'/prev' itself (12 contiguous
+// bytes per triangle); the label and loop bytes go out through LDS in whole
+// words.
 // ---------------------------------------------------------------------------
 
 // Loop byte of the minimum's triangle: (min(len, kPlMax) << 2) | local
