@@ -126,6 +126,16 @@ struct RunBuffers {
 constexpr int kWalkBuf = 16;
 constexpr int kWalkItems = 1;   // chains per k_walk thread
 constexpr int kScanChunk = 1024;   // compaction tiles per k_tile_scan block
+// k_compact's LDS holds up to this many loop half-edges per 4 triangles of
+// its tile (2.75 per triangle; meshes average about 2 or fewer).  A tile
+// with more writes its loops straight to global memory.  With one seed and
+// one offset per triangle that is 19 bytes per triangle, so eight tiles of
+// 1024 triangles share a CU's LDS.
+constexpr int kCompactHe4 = 11;
+__host__ __device__ inline int compact_he_cap(int tile) { return tile / 4 * kCompactHe4; }
+inline size_t compact_lds_bytes(int tile) {
+    return sizeof(int) * ((size_t)compact_he_cap(tile) + 2 * (size_t)tile);
+}
 
 enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];

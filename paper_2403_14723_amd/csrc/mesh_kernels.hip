@@ -1295,13 +1295,14 @@ template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
                                                   const uint64_t *status, const uint64_t *cpre, EmitEntry *emit,
                                                   int32_t *emit_counts, int emit_cap, const int32_t *wbuf) {
-    // LDS: loop half-edges (3 per triangle of the tile), seeds and local
-    // offsets (one per triangle)
+    // LDS: loop half-edges (compact_he_cap of them), seeds and local offsets
+    // (one per triangle)
     extern __shared__ int4 lds_raw[];
     const int B = blockDim.x, tid = threadIdx.x;
     const int TB = B * ITEMS;
+    const int he_cap = compact_he_cap(TB);
     int *s_he = reinterpret_cast<int *>(lds_raw);
-    int *s_seed = s_he + 3 * TB;
+    int *s_seed = s_he + he_cap;
     int *s_off = s_seed + TB;
     __shared__ int s_scan[72];
     __shared__ int s_ebase;
@@ -1370,7 +1371,7 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         // the tiles' prefixes must add up to the mesh totals
         if (ltile == mesh_tiles - 1 && (pc + tcnt != d.ctr->npoly || ps + tsum != d.ctr->nloop)) bad = true;
     }
-    const bool fits = tsum <= 3 * TB && pc + tcnt <= nt && ps + tsum <= nh;
+    const bool fits = tsum <= he_cap && pc + tcnt <= nt && ps + tsum <= nh;
     // 3. seeds, local offsets and loops; into LDS, or straight to global
     //    memory for a tile whose loops do not fit
     // A loop of 3 is one triangle: (mn, next, prev).  A loop of 4 is two
@@ -1572,7 +1573,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
 
     H(K_COMPACT, 0);
     GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
-                    sizeof(int) * 5 * (size_t)cfg.block_compact * cfg.items_compact, s, rb.descs, rb.nmesh,
+                    compact_lds_bytes(cmp_tb), s, rb.descs, rb.nmesh,
                     rb.status, rb.cpre, rb.emit, rb.emit_counts, rb.emit_cap, rb.wbuf);
     H(K_COMPACT, 1);
 

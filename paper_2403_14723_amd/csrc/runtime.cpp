@@ -489,7 +489,7 @@ int parse_launch_spec(const char *spec, gp::LaunchCfg *cfg) {
         }
     }
     // LDS per tile: k_label stages 12 bytes per triangle (tile <= 4096),
-    // k_relink 19 bytes (tile <= 1024), k_compact 20 bytes (tile <= 2048)
+    // k_relink 19 bytes (tile <= 1024), k_compact 19 bytes (tile <= 2048)
     while ((int64_t)g.block_label * g.items_label > 4096 && g.items_label > 1) g.items_label /= 2;
     while ((int64_t)g.block_relink * g.items_relink > 1024 && g.items_relink > 1) g.items_relink /= 2;
     while ((int64_t)g.block_compact * g.items_compact > 2048 && g.items_compact > 1) g.items_compact /= 2;

@@ -186,6 +186,29 @@ def grid_band(m: Mesh, n: int, band: int, nbands: int, halo: int = 2) -> Mesh:
                 f"{m.name or 'grid'}_band{band}of{nbands}")
 
 
+def flat_strip(n: int, name: str = "") -> Mesh:
+    """2n-1 flat triangles between two horizontal lines: bases of length w on
+    the lines alternate with shared sides of length sqrt(w^2/4 + h^2) < w
+    (h = w/4).  Every longest edge is a boundary edge and no shared side is
+    the longest edge of either triangle, so every triangle is a polygon of
+    its own: P = T and Fh = 3T, the most loop half-edges a mesh can have."""
+    if not (1 <= n <= 1 << 20):
+        raise ValueError("n must be in [1, 2**20]")
+    w = DOMAIN // n
+    h = w // 4
+    bot = np.stack([np.arange(n + 1, dtype=np.int64) * w, np.zeros(n + 1, np.int64)], -1)
+    top = np.stack([np.arange(n, dtype=np.int64) * w + w // 2, np.full(n, h, np.int64)], -1)
+    xy = np.concatenate([bot, top]).astype(np.int32)
+    i = np.arange(n)
+    up = np.stack([i, i + 1, n + 1 + i], -1)                  # (b_i, b_i+1, t_i)
+    j = np.arange(n - 1)
+    down = np.stack([n + 1 + j, j + 1, n + 2 + j], -1)       # (t_j, b_j+1, t_j+1)
+    tri = np.empty((2 * n - 1, 3), np.int64)
+    tri[0::2] = up
+    tri[1::2] = down
+    return Mesh(np.ascontiguousarray(xy), np.ascontiguousarray(tri.astype(np.int32)), name or f"flat_strip{n}")
+
+
 # ---------------------------------------------------------------------------
 # The five workloads
 # ---------------------------------------------------------------------------

@@ -313,3 +313,12 @@ def test_grid_bands(ctx):
         for key in ("next", "prev"):
             got = g[key][lo:hi]
             np.testing.assert_array_equal(np.where(got >= 0, got + off, -1), whole[key][lo + off:hi + off])
+
+
+@pytest.mark.parametrize("n", [600, 5000])
+def test_flat_strip_every_triangle_a_polygon(ctx, n):
+    """Three loop half-edges per triangle, more than a compaction tile keeps
+    in LDS: those tiles write their loops straight to global memory."""
+    m = W.flat_strip(n)
+    g, o = check_case(ctx, m.xy, m.tri, m.name)
+    assert o.stats["npoly"] == m.nt

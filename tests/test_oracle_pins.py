@@ -236,3 +236,24 @@ def test_empty_and_unused_vertices():
     xy = np.array([[0, 0], [10, 0], [0, 10], [77, 77]], np.int32)
     res = oracle.polylla(xy, np.array([[0, 1, 2]], np.int32))
     assert res.stats["npoly"] == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 500])
+def test_flat_strip_closed_form(n):
+    """Flat triangles whose longest edges all lie on the boundary, where a
+    Lepp ends at once (Section 3.1, Definitions 1-2; terminal edges may be
+    border edges), and whose shared sides are the longest edge of neither
+    neighbour, so frontier (Definition 3): each triangle is a terminal-edge
+    region and a polygon of its own, and its loop is its three half-edges in
+    order."""
+    m = W.flat_strip(n)
+    o = oracle.polylla(m.xy, m.tri)
+    T = m.nt
+    h = np.arange(3 * T)
+    assert T == 2 * n - 1
+    assert o.stats["npoly"] == T and o.stats["nloop_he"] == 3 * T and o.stats["ntips"] == 0
+    np.testing.assert_array_equal(o.seeds, 3 * np.arange(T))
+    np.testing.assert_array_equal(o.loop_off, 3 * np.arange(T + 1))
+    np.testing.assert_array_equal(o.loop_he, h)
+    np.testing.assert_array_equal(o.next, 3 * (h // 3) + (h % 3 + 1) % 3)
+    np.testing.assert_array_equal(o.prev, 3 * (h // 3) + (h % 3 + 2) % 3)
