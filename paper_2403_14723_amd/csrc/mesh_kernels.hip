@@ -1476,13 +1476,36 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         place_loops((gint)d.loop_he + ps);
     if (fits) {
         __syncthreads();
-        // contiguous stores of the tile's part of seeds, loop_off, loop_he
+        // contiguous stores of the tile's part of seeds, loop_off, loop_he;
+        // all of a thread's LDS reads are issued before its first store
+        constexpr int kSeedIt = ITEMS;                  // tcnt <= TB
+        constexpr int kHeIt = (kCompactHe4 * ITEMS + 3) / 4;   // tsum <= he_cap
         const gint seeds = (gint)d.seeds, loff = (gint)d.loop_off, lhe = (gint)d.loop_he;
-        for (int k = tid; k < tcnt; k += B) {
-            seeds[pc + k] = s_seed[k];
-            loff[pc + k] = ps + s_off[k];
+        int vs[kSeedIt], vo[kSeedIt], vh[kHeIt];
+#pragma unroll
+        for (int it = 0; it < kSeedIt; it++) {
+            const int k = tid + it * B;
+            vs[it] = s_seed[k < tcnt ? k : 0];
+            vo[it] = s_off[k < tcnt ? k : 0];
         }
-        for (int k = tid; k < tsum; k += B) lhe[ps + k] = s_he[k];
+#pragma unroll
+        for (int it = 0; it < kHeIt; it++) {
+            const int k = tid + it * B;
+            vh[it] = s_he[k < tsum ? k : 0];
+        }
+#pragma unroll
+        for (int it = 0; it < kSeedIt; it++) {
+            const int k = tid + it * B;
+            if (k < tcnt) {
+                seeds[pc + k] = vs[it];
+                loff[pc + k] = ps + vo[it];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kHeIt; it++) {
+            const int k = tid + it * B;
+            if (k < tsum) lhe[ps + k] = vh[it];
+        }
     }
     if (bad) atomicOr(&d.ctr->err, kErrCorrupt);
 }
