@@ -91,8 +91,8 @@ constexpr int kStripePad = 32;   // counters 128 bytes apart: one cache line eac
 struct LaunchCfg {
     int block_label = 128, items_label = 4;
     int block_relink = 256, items_relink = 2;     // k_relink (tile <= 1024 triangles)
-    int block_compact = 256, items_compact = 4;   // tile <= 2048 triangles (LDS 20 B each)
-    int persistent_blocks = 4096;
+    int block_compact = 128, items_compact = 4;   // tile <= 2048 triangles (LDS 19 B each)
+    int persistent_blocks = 2048;
     int block_persistent = 256;
 };
 
