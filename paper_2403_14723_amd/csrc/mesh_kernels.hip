@@ -385,15 +385,19 @@ constexpr int kPlQuadNext = 1;
 // Records a walked loop (minimum mn, length len) once: the walker that sets
 // the byte of the minimum's triangle adds the loop to the totals of that
 // triangle's compaction tile.  After a repair several seeds of one polygon
-// walk the same loop; only the first counts it.
-__device__ __forceinline__ bool claim_loop(const MeshDesc &d, int mn, int len, uint64_t *agg, int cmp_tb) {
+// walk the same loop; only the first counts it.  claim_issue ORs the code in
+// and returns the word as it was (every walker of the loop writes the same
+// code, so OR-ing is safe); claim_won reads the verdict from it, so other
+// memory operations can be issued while the atomic is in flight.
+__device__ __forceinline__ uint32_t claim_issue(const MeshDesc &d, int mn, int len) {
     const int tm = tri_of(mn);
-    const uint32_t code = loop_code(mn, len);
     uint32_t *w = reinterpret_cast<uint32_t *>(d.pl) + (tm >> 2);
-    const int sh = 8 * (tm & 3);
-    // every walker of this loop writes the same code, so OR-ing it in is
-    // safe; the one that found the byte empty counts the loop
-    if ((atomicOr(w, code << sh) >> sh) & 0xffu) return false;
+    return atomicOr(w, (uint32_t)loop_code(mn, len) << (8 * (tm & 3)));
+}
+__device__ __forceinline__ bool claim_won(const MeshDesc &d, uint32_t old, int mn, int len, uint64_t *agg,
+                                          int cmp_tb) {
+    const int tm = tri_of(mn);
+    if ((old >> (8 * (tm & 3))) & 0xffu) return false;
     atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + tm / cmp_tb),
               (1ull << 32) | (unsigned long long)(uint32_t)len);
     return true;
@@ -1061,7 +1065,9 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
 // copies it to the scratch pool (rotation index of the minimum, then the
 // half-edges in walk order) and k_compact places it without walking it
 // again.  Whole waves iterate together: the pool is reserved once per wave
-// and step.
+// and step, for every loop that closed in that step and fits the buffer,
+// while the claims are still in flight (a walker that loses the claim leaves
+// its space unused).
 template <int ITEMS, int BUF>
 __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
                                               const int32_t *walk_counts, int walk_cap, uint64_t *agg,
@@ -1105,9 +1111,13 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
         while (true) {
             bool active = false;
             int need[ITEMS];
+            bool closed[ITEMS];
+            uint32_t claim[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
                 need[j] = 0;
+                closed[j] = false;
+                claim[j] = 0;
                 if (start[j] < 0) continue;
                 if (len[j] < BUF) s_buf[len[j] * kSlots + j * 256 + tid] = cur[j];
                 if (cur[j] < mn[j]) {
@@ -1122,9 +1132,10 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                     continue;
                 }
                 if (cur[j] == start[j]) {
-                    const bool win = claim_loop(descs[mesh[j]], mn[j], len[j], agg, cmp_tb);
+                    closed[j] = true;
+                    claim[j] = claim_issue(descs[mesh[j]], mn[j], len[j]);
                     // whole 16-byte groups, so k_compact reads a loop with vector loads
-                    need[j] = win && len[j] <= BUF ? (len[j] + 4) & ~3 : 0;
+                    need[j] = len[j] <= BUF ? (len[j] + 4) & ~3 : 0;
                     start[j] = -1;
                     continue;
                 }
@@ -1139,20 +1150,22 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
             int wbase = 0;
             if (lane == 0 && wtot > 0) wbase = atomicAdd(&wbuf_counts[wstripe * kStripePad], wtot);
             wbase = __builtin_amdgcn_readlane(wbase, 0);
-            if (mine > 0 && wbase + wtot <= wbuf_cap) {
-                int pos = wstripe * wbuf_cap + wbase + incl - mine;
+            const bool room = wbase + wtot <= wbuf_cap;
+            int pos = wstripe * wbuf_cap + wbase + incl - mine;
 #pragma unroll
-                for (int j = 0; j < ITEMS; j++) {
-                    if (!need[j]) continue;
-                    const MeshDesc &d = descs[mesh[j]];
+            for (int j = 0; j < ITEMS; j++) {
+                if (!closed[j]) continue;
+                const MeshDesc &d = descs[mesh[j]];
+                const bool won = claim_won(d, claim[j], mn[j], len[j], agg, cmp_tb);
+                if (won && need[j] && room) {
                     const gint out = (gint)wbuf + pos;
                     out[0] = rot[j];
                     for (int k = 0; k < len[j]; k++) out[1 + k] = s_buf[k * kSlots + j * 256 + tid];
                     const int tm = tri_of(mn[j]);
                     ((gint)d.lpos)[tm] = pos;
                     atomicOr(reinterpret_cast<uint32_t *>(d.tflag) + (tm >> 2), kStoredBit << (8 * (tm & 3)));
-                    pos += need[j];
                 }
+                pos += need[j];
             }
             if (!__any(active)) break;
         }
