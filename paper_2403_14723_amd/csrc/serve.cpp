@@ -1,16 +1,16 @@
 // Serving loop: continuous batching of meshing requests on one GPU.
 //
-// Requests (a triangulation each) are copied at submit and queued.  One
-// worker thread runs `lanes`, each an internal context with its own stream
-// and a fixed device arena.  Whenever a lane is free and requests are queued,
-// the worker admits as many queued requests as fit the lane's arena (their
-// exact device footprint) up to max_batch, builds their half-edge structures
-// and launches one batched meshing run on that lane.  While it runs, the
-// other lanes take the requests that keep arriving, so batches overlap on the
-// device.  When a lane's kernels finish, its outputs are copied to pinned
-// host blocks (exact sizes, known from the run's counts); when the copies
-// finish, every request of the batch completes with a host-resident result
-// and the lane's arena is reset.  Latency runs from submit to that point.
+// Requests (a triangulation each) are copied at submit and queued.  The server runs `lanes`, each an internal context with
+// its own stream, a fixed device arena and a thread of its own.  A lane's
+// thread admits as many queued requests as fit the arena (their exact device
+// footprint) up to max_batch, builds their half-edge structures and
+// launches one batched meshing run.  While it
+// runs, the other lanes take the requests that keep arriving, so uploads,
+// builds, runs and downloads of different batches overlap.  When a lane's
+// kernels finish, its outputs are copied to pinned host blocks (exact sizes,
+// known from the run's counts); when the copies finish, every request of the
+// batch completes with a host-resident result and the lane's arena is reset.
+// Latency runs from submit to that point.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -99,7 +99,7 @@ struct gp_server {
     size_t lane_bytes = 0;
     std::vector<Lane> lanes;
     std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>();
-    std::thread worker;
+    std::vector<std::thread> workers;   // one per lane
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
@@ -255,30 +255,6 @@ void finish(gp_server *s, Lane &L) {
     L.state = Lane::FREE;
 }
 
-// Advances every lane whose GPU work has finished; returns whether any did.
-bool poll_lanes(gp_server *s) {
-    bool moved = false;
-    for (Lane &L : s->lanes) {
-        if (L.state == Lane::RUNNING) {
-            // nothing else is queued on the lane's stream while it runs
-            const hipError_t q = hipStreamQuery(L.ctx->stream);
-            if (q != hipErrorNotReady) {
-                if (q != hipSuccess) (void)hipGetLastError();
-                start_copies(s, L);
-                moved = true;
-            }
-        } else if (L.state == Lane::COPYING) {
-            const hipError_t q = hipEventQuery(L.copied);
-            if (q != hipErrorNotReady) {
-                if (q != hipSuccess) (void)hipGetLastError();
-                finish(s, L);
-                moved = true;
-            }
-        }
-    }
-    return moved;
-}
-
 // Device bytes of a batch on one lane: every build plus the batched run.
 size_t batch_bytes(const gp::LaunchCfg &cfg, const std::vector<Request *> &b, const Request *extra) {
     std::vector<int32_t> nts;
@@ -294,40 +270,40 @@ size_t batch_bytes(const gp::LaunchCfg &cfg, const std::vector<Request *> &b, co
     return sum + batch_footprint(cfg, nts.data(), (int)nts.size());
 }
 
-void worker_main(gp_server *s) {
+// One lane's thread: admit a batch, build and mesh it, copy the results out,
+// hand them over, repeat; on stop, drain the queue first.
+void lane_main(gp_server *s, Lane *L) {
     DeviceGuard g(s->device);
     while (true) {
-        bool moved = poll_lanes(s);
-        Lane *free_lane = nullptr;
-        for (Lane &L : s->lanes)
-            if (L.state == Lane::FREE) {
-                free_lane = &L;
-                break;
-            }
         std::vector<Request *> batch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            bool busy = false;
-            for (Lane &L : s->lanes) busy |= L.state != Lane::FREE;
-            if (s->stopping && s->queue.empty() && !busy) break;
-            if (free_lane && !s->queue.empty()) {
-                // admission by footprint: as many queued requests as fit
-                while (!s->queue.empty() && (int)batch.size() < s->opts.max_batch) {
-                    Request *r = s->queue.front();
-                    if (batch_bytes(free_lane->ctx->cfg, batch, r) > s->lane_bytes) break;
-                    batch.push_back(r);
-                    s->queue.pop_front();
-                }
+            s->cv_work.wait(lk, [s] { return s->stopping || !s->queue.empty(); });
+            if (s->queue.empty()) break;   // stopping, nothing left
+            // admission by footprint: as many queued requests as fit
+            while (!s->queue.empty() && (int)batch.size() < s->opts.max_batch) {
+                Request *r = s->queue.front();
+                if (batch_bytes(L->ctx->cfg, batch, r) > s->lane_bytes) break;
+                batch.push_back(r);
+                s->queue.pop_front();
             }
-            if (batch.empty() && !moved) {
-                // nothing to launch: sleep briefly, or until a submit
-                if (busy)
-                    s->cv_work.wait_for(lk, std::chrono::microseconds(50));
-                else
-                    s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            if (batch.empty()) {
+                // submit rejects requests larger than a lane, so an empty lane
+                // fits the first one; never spin on one that does not
+                Request *r = s->queue.front();
+                s->queue.pop_front();
+                lk.unlock();
+                complete(s, r, GP_ETOOBIG, nullptr);
+                continue;
             }
+            if (!s->queue.empty()) s->cv_work.notify_one();   // work left for another lane
         }
-        if (!batch.empty()) launch(s, *free_lane, batch);
+        launch(s, *L, batch);
+        if (L->state != Lane::RUNNING) continue;   // every build failed
+        if (hipStreamSynchronize(L->ctx->stream) != hipSuccess) (void)hipGetLastError();
+        start_copies(s, *L);
+        if (hipEventSynchronize(L->copied) != hipSuccess) (void)hipGetLastError();
+        finish(s, *L);
     }
 }
 
@@ -377,7 +353,7 @@ int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out
             return rc;
         }
     }
-    s->worker = std::thread(worker_main, s);
+    for (Lane &L : s->lanes) s->workers.emplace_back(lane_main, s, &L);
     *out = s;
     return GP_OK;
 }
@@ -415,6 +391,10 @@ int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int
     r->tri.assign(tri, tri + 3 * (size_t)nt);
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) {   // stopped while the inputs were copied: the lanes may be gone
+            delete r;
+            return GP_EINVAL;
+        }
         r->ticket = s->next_ticket++;
         s->reqs[r->ticket] = r;
         s->queue.push_back(r);
@@ -489,7 +469,8 @@ int gpolylla_serve_stop(gp_server *s) {
         s->stopping = true;
     }
     s->cv_work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    for (std::thread &t : s->workers)
+        if (t.joinable()) t.join();
     {
         DeviceGuard g(s->device);
         for (Lane &L : s->lanes) {
