@@ -70,6 +70,34 @@ struct PinnedPool {
     }
 };
 
+// Host buffers for requests' inputs, kept after a request completes and
+// handed to later submits: a reused buffer copies at memory speed, a fresh
+// one takes a page fault per page first.  At most kCap bytes are kept.
+struct InputPool {
+    static constexpr size_t kCap = (size_t)2 << 30;
+    std::mutex mu;
+    std::multimap<size_t, std::vector<int32_t>> free_;   // by capacity (elements)
+    size_t bytes = 0;
+    std::vector<int32_t> take(size_t n) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = free_.lower_bound(n);
+        if (it == free_.end() || it->first > 2 * n + 4096) return {};
+        std::vector<int32_t> v = std::move(it->second);
+        bytes -= sizeof(int32_t) * it->first;
+        free_.erase(it);
+        return v;
+    }
+    void give(std::vector<int32_t> &&v) {
+        v.clear();
+        const size_t c = v.capacity();
+        if (!c) return;
+        std::lock_guard<std::mutex> lk(mu);
+        if (bytes + sizeof(int32_t) * c > kCap) return;   // dropped: freed with v
+        bytes += sizeof(int32_t) * c;
+        free_.emplace(c, std::move(v));
+    }
+};
+
 struct Lane {
     gp_ctx *ctx = nullptr;
     enum State { FREE, RUNNING, COPYING } state = FREE;
@@ -99,6 +127,7 @@ struct gp_server {
     size_t lane_bytes = 0;
     std::vector<Lane> lanes;
     std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>();
+    InputPool inputs;
     std::vector<std::thread> workers;   // one per lane
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -116,6 +145,8 @@ struct gp_server {
 namespace {
 
 void complete(gp_server *s, Request *r, int status, gp_result *res) {
+    s->inputs.give(std::move(r->xy));   // the build has read them
+    s->inputs.give(std::move(r->tri));
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     r->status = status;
@@ -129,10 +160,6 @@ void complete(gp_server *s, Request *r, int status, gp_result *res) {
     } else {
         s->failed++;
     }
-    r->xy.clear();
-    r->xy.shrink_to_fit();
-    r->tri.clear();
-    r->tri.shrink_to_fit();
     s->cv_done.notify_all();
 }
 
@@ -387,6 +414,8 @@ int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int
             return GP_EAGAIN;
         }
     }
+    r->xy = s->inputs.take(2 * (size_t)nv);
+    r->tri = s->inputs.take(3 * (size_t)nt);
     r->xy.assign(xy, xy + 2 * (size_t)nv);
     r->tri.assign(tri, tri + 3 * (size_t)nt);
     {
