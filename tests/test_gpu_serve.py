@@ -90,3 +90,22 @@ def test_served_errors(ctx):
         with pytest.raises(gp.GPolyllaError) as e:
             srv.wait(12345678, 10)
         assert e.value.code == gp.GP_EINVAL
+
+
+def test_stop_drains_requests_in_flight(ctx):
+    """Stopping a server with requests still queued and running finishes them
+    all (each lane drains the queue before its thread ends); results never
+    waited for are released by the stop."""
+    reqs = [W.jittered_grid(n, seed=600 + n, warp=(n % 2 == 0)) for n in (40, 90, 150, 200, 64, 7, 128, 99)]
+    srv = gp.Server(ctx, pool_bytes=1 << 30, max_batch=3, n_lanes=3)
+    say("[gpu] serve: stop with requests in flight")
+    first = srv.submit(reqs[0].xy, reqs[0].tri)
+    r = srv.wait(first, 60000)
+    o = oracle.polylla(reqs[0].xy, reqs[0].tri)
+    assert np.array_equal(r.copy()["loop_he"], o.loop_he)
+    r.free()
+    for m in reqs * 4:
+        srv.submit(m.xy, m.tri)
+    st = srv.stats()
+    assert st["submitted"] == 1 + 4 * len(reqs)
+    srv.stop()   # returns once every lane has drained the queue
