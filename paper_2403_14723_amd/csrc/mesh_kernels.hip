@@ -518,7 +518,16 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     int *s_tip = s_q + 2 * qcap;                                // barrier tips found here
     const int tcap = TB / 4;
     __shared__ int s_ntip;
+    // loops settled here, per compaction tile, when the tile's triangles
+    // span several of them (a relink tile of <= 1024 triangles, compaction
+    // tiles of >= 64: at most 17)
+    constexpr int kSpan = 1024 / 64 + 1;
+    __shared__ int s_aggc[kSpan], s_aggl[kSpan];
     if (threadIdx.x == 0) s_ntip = 0;
+    if (threadIdx.x < kSpan) {
+        s_aggc[threadIdx.x] = 0;
+        s_aggl[threadIdx.x] = 0;
+    }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int mi = find_mesh<1>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
@@ -704,14 +713,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
                 atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + base / cmp_tb),
                           ((unsigned long long)(uint32_t)(tb >> 16) << 32) | (unsigned long long)(tb & 0xffff));
         }
-        if (!one) {
+        const int ct0 = base / cmp_tb;   // first compaction tile of this tile
+        if (!one) {   // totals per compaction tile in LDS, one global atomic each below
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
                 if (!codes[j]) continue;
-                const int t = base + j * B + tid;
+                const int k = (base + j * B + tid) / cmp_tb - ct0;
                 const int len = (codes[j] >> 2) == kPlQuadNext ? 4 : (codes[j] >> 2);
-                atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + t / cmp_tb),
-                          (1ull << 32) | (unsigned long long)len);
+                atomicAdd(&s_aggc[k], 1);
+                atomicAdd(&s_aggl[k], len);
             }
         }
 #pragma unroll
@@ -727,6 +737,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             ++eq;
         }
         __syncthreads();
+        if (!one && tid <= (base + cnt - 1) / cmp_tb - ct0 && s_aggc[tid] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + ct0 + tid),
+                      ((unsigned long long)(uint32_t)s_aggc[tid] << 32) | (unsigned long long)(uint32_t)s_aggl[tid]);
         const int wbase = s_wbase;
         err |= wbase + to > walk_cap;
         int e = stripe * walk_cap + wbase + eo;
