@@ -5,7 +5,8 @@
 //   k_orient     index check, exact int64 orientation test, counter-clockwise
 //                corner order, out-degree count per vertex
 //   k_scan_excl  exclusive scan of the out-degrees (decoupled look-back)
-//   k_bucket     half-edges grouped by origin vertex (CSR)
+//   k_bucket     half-edges grouped by origin vertex (CSR), each with its
+//                target vertex beside it
 //   k_match      twin(h) for h = u->v: the half-edge v->u in v's bucket; a
 //                second u->v in u's bucket, or two v->u, is non-manifold
 //
@@ -153,31 +154,31 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_excl(const int32_t *__restr
 }
 
 __global__ void k_bucket(const int32_t *__restrict__ org, int nh, const int32_t *__restrict__ vstart,
-                         int32_t *fill, int32_t *bucket) {
+                         int32_t *fill, int2 *bucket) {
     for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
         int v = org[h];
         int slot = vstart[v] + atomicAdd(&fill[v], 1);
-        bucket[slot] = h;
+        bucket[slot] = make_int2(h, org[he_next_b(h)]);
     }
 }
 
 __global__ void k_match(const int32_t *__restrict__ org, int nt, const int32_t *__restrict__ vstart,
-                        const int32_t *__restrict__ bucket, int32_t *__restrict__ twin,
+                        const int2 *__restrict__ bucket, int32_t *__restrict__ twin,
                         unsigned long long *err) {
     const int nh = 3 * nt;
     for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
         int u = org[h], v = org[he_next_b(h)];
         int found = -1, nrev = 0, ndup = 0;
         for (int k = vstart[v], e = vstart[v + 1]; k < e; k++) {
-            int g = bucket[k];
-            if (org[he_next_b(g)] == u) {
-                found = g;
+            const int2 g = bucket[k];   // (half-edge v->w, w)
+            if (g.y == u) {
+                found = g.x;
                 ++nrev;
             }
         }
         for (int k = vstart[u], e = vstart[u + 1]; k < e; k++) {
-            int g = bucket[k];
-            if (g != h && org[he_next_b(g)] == v) ++ndup;
+            const int2 g = bucket[k];
+            if (g.x != h && g.y == v) ++ndup;
         }
         if (nrev > 1 || ndup > 0) atomicMin(err, err_key(1ull + nt + h, -4));
         twin[h] = nrev == 1 ? found : -1;

@@ -167,7 +167,7 @@ struct BuildBuffers {
     int32_t *deg;      // nv + 1, zeroed by the build
     int32_t *vstart;   // nv + 1
     int32_t *fill;     // nv
-    int32_t *bucket;   // 3 nt
+    int2 *bucket;      // 3 nt: (half-edge, its target vertex), grouped by origin
     uint64_t *scan_status;  // scan tiles
     int32_t *scan_ctr;
     unsigned long long *err_key;  // lowest (rank << 8 | code) seen

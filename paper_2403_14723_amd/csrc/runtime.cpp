@@ -303,7 +303,7 @@ size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device) {
     const int64_t nh = 3 * nt;
     const size_t keep = align_up(sizeof(int2) * (size_t)std::max<int64_t>(nv, 1)) +
                         2 * align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1));
-    const size_t tmp = arena_bytes<int32_t>(nv + 1) * 3 + arena_bytes<int32_t>(nh + 1) +
+    const size_t tmp = arena_bytes<int32_t>(nv + 1) * 3 + arena_bytes<int2>(nh + 1) +
                        arena_bytes<uint64_t>(gp::build_scan_tiles((int32_t)nv)) + arena_bytes<int32_t>(4) +
                        arena_bytes<unsigned long long>(1) + (inputs_on_device ? 0 : arena_bytes<int32_t>(nh + 1));
     return keep + align_up(tmp);
@@ -651,7 +651,7 @@ int gpolylla_build_halfedges(gp_ctx *c, const int32_t *xy, int32_t nv, const int
     if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1), &p_twin);
     const int32_t scan_tiles = gp::build_scan_tiles(nv);
     const size_t tmp_bytes = arena_bytes<int32_t>(nv + 1) * 2 + arena_bytes<int32_t>(nv + 1) +
-                             arena_bytes<int32_t>(nh + 1) + arena_bytes<uint64_t>(scan_tiles) +
+                             arena_bytes<int2>(nh + 1) + arena_bytes<uint64_t>(scan_tiles) +
                              arena_bytes<int32_t>(4) + arena_bytes<unsigned long long>(1) +
                              (in_dev ? 0 : arena_bytes<int32_t>(nh + 1));
     if (rc == GP_OK) rc = c->pool.alloc(tmp_bytes, &p_tmp);
@@ -675,7 +675,7 @@ int gpolylla_build_halfedges(gp_ctx *c, const int32_t *xy, int32_t nv, const int
     b.deg = a.take<int32_t>(nv + 1);
     b.fill = a.take<int32_t>(nv + 1);
     b.vstart = a.take<int32_t>(nv + 1);
-    b.bucket = a.take<int32_t>(nh + 1);
+    b.bucket = a.take<int2>(nh + 1);
     b.scan_status = a.take<uint64_t>(scan_tiles);
     int32_t *small = a.take<int32_t>(4);
     b.scan_ctr = small;
