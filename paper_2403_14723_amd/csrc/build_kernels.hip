@@ -24,6 +24,29 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr uint64_t kScanAgg = 1ull << 62;
 constexpr uint64_t kScanInc = 2ull << 62;
+// k_orient and k_bucket work in tiles of 256 threads x kTileItems items and
+// count per vertex in an LDS histogram when the tile's vertex ids span at
+// most kHistBins (meshes numbered row by row or along a curve do): one
+// global atomic per distinct vertex of the tile instead of one per corner
+constexpr int kTileItems = 4;
+constexpr int kHistBins = 8192;
+
+// [lo, hi] of the values v over the block (hi < lo when no thread has one);
+// every thread calls it, s_lohi is shared
+__device__ __forceinline__ void block_range(int vlo, int vhi, int *s_lohi, int &lo, int &hi) {
+    if (threadIdx.x == 0) {
+        s_lohi[0] = 0x7fffffff;
+        s_lohi[1] = -1;
+    }
+    __syncthreads();
+    if (vhi >= vlo) {
+        atomicMin(&s_lohi[0], vlo);
+        atomicMax(&s_lohi[1], vhi);
+    }
+    __syncthreads();
+    lo = s_lohi[0];
+    hi = s_lohi[1];
+}
 
 __device__ __forceinline__ unsigned long long err_key(unsigned long long rank, int code) {
     return (rank << 8) | (unsigned long long)(-code);
@@ -41,40 +64,79 @@ __global__ void k_check_xy(const int2 *__restrict__ xy, int nv, unsigned long lo
     }
 }
 
-__global__ void k_orient(const int2 *__restrict__ xy, const int32_t *__restrict__ tri, int nv, int nt,
-                         int32_t *__restrict__ org, int32_t *__restrict__ deg,
-                         unsigned long long *err, int32_t *nflipped) {
-    for (int base = blockIdx.x * blockDim.x; base < nt; base += gridDim.x * blockDim.x) {
-        int t = base + threadIdx.x;
-        bool flip = false;
-        if (t < nt) {
-            int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
-            if ((unsigned)a >= (unsigned)nv || (unsigned)b >= (unsigned)nv || (unsigned)c >= (unsigned)nv) {
-                atomicMin(err, err_key(1ull + t, -1));
-            } else {
-                int2 pa = xy[a], pb = xy[b], pc = xy[c];
-                long long o = ((long long)pb.x - pa.x) * ((long long)pc.y - pa.y) -
-                              ((long long)pb.y - pa.y) * ((long long)pc.x - pa.x);
-                if (o == 0) {
-                    atomicMin(err, err_key(1ull + t, -3));
+__global__ void __launch_bounds__(256) k_orient(const int2 *__restrict__ xy, const int32_t *__restrict__ tri,
+                                                 int nv, int nt, int32_t *__restrict__ org,
+                                                 int32_t *__restrict__ deg, unsigned long long *err,
+                                                 int32_t *nflipped) {
+    __shared__ int s_hist[kHistBins];
+    __shared__ int s_lohi[2];
+    const int TB = 256 * kTileItems;
+    for (int base = blockIdx.x * TB; base < nt; base += gridDim.x * TB) {   // block-uniform
+        int cv[kTileItems][3];
+        bool ok[kTileItems];
+        int vlo = 0x7fffffff, vhi = -1, nflip = 0;
+#pragma unroll
+        for (int j = 0; j < kTileItems; j++) {
+            const int t = base + j * 256 + threadIdx.x;
+            ok[j] = false;
+            bool flip = false;
+            if (t < nt) {
+                int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+                if ((unsigned)a >= (unsigned)nv || (unsigned)b >= (unsigned)nv || (unsigned)c >= (unsigned)nv) {
+                    atomicMin(err, err_key(1ull + t, -1));
                 } else {
-                    if (o < 0) {
-                        int s = b;
-                        b = c;
-                        c = s;
-                        flip = true;
+                    int2 pa = xy[a], pb = xy[b], pc = xy[c];
+                    long long o = ((long long)pb.x - pa.x) * ((long long)pc.y - pa.y) -
+                                  ((long long)pb.y - pa.y) * ((long long)pc.x - pa.x);
+                    if (o == 0) {
+                        atomicMin(err, err_key(1ull + t, -3));
+                    } else {
+                        if (o < 0) {
+                            int s = b;
+                            b = c;
+                            c = s;
+                            flip = true;
+                        }
+                        org[3 * t] = a;
+                        org[3 * t + 1] = b;
+                        org[3 * t + 2] = c;
+                        cv[j][0] = a;
+                        cv[j][1] = b;
+                        cv[j][2] = c;
+                        ok[j] = true;
+                        vlo = min(vlo, min(a, min(b, c)));
+                        vhi = max(vhi, max(a, max(b, c)));
                     }
-                    org[3 * t] = a;
-                    org[3 * t + 1] = b;
-                    org[3 * t + 2] = c;
-                    atomicAdd(&deg[a], 1);
-                    atomicAdd(&deg[b], 1);
-                    atomicAdd(&deg[c], 1);
                 }
             }
+            const unsigned long long m = __ballot(flip);
+            nflip += __popcll(m);
         }
-        unsigned long long m = __ballot(flip);
-        if (m && __lane_id() == __ffsll((long long)m) - 1) atomicAdd(nflipped, __popcll(m));
+        if (nflip && __lane_id() == 0) atomicAdd(nflipped, nflip);
+        int lo, hi;
+        block_range(vlo, vhi, s_lohi, lo, hi);
+        if (hi >= lo && hi - lo < kHistBins) {   // block-uniform
+            const int range = hi - lo + 1;
+            for (int k = threadIdx.x; k < range; k += 256) s_hist[k] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kTileItems; j++)
+                if (ok[j])
+#pragma unroll
+                    for (int i = 0; i < 3; i++) atomicAdd(&s_hist[cv[j][i] - lo], 1);
+            __syncthreads();
+            for (int k = threadIdx.x; k < range; k += 256) {
+                const int n = s_hist[k];
+                if (n) atomicAdd(&deg[lo + k], n);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kTileItems; j++)
+                if (ok[j])
+#pragma unroll
+                    for (int i = 0; i < 3; i++) atomicAdd(&deg[cv[j][i]], 1);
+        }
+        __syncthreads();   // the histogram and range are reused by the next tile
     }
 }
 
@@ -153,12 +215,54 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_excl(const int32_t *__restr
     if (tile == (last_tile < 0 ? 0 : last_tile) && threadIdx.x == kScanBlock - 1) out[n] = run;
 }
 
-__global__ void k_bucket(const int32_t *__restrict__ org, int nh, const int32_t *__restrict__ vstart,
-                         int32_t *fill, int2 *bucket) {
-    for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < nh; h += gridDim.x * blockDim.x) {
-        int v = org[h];
-        int slot = vstart[v] + atomicAdd(&fill[v], 1);
-        bucket[slot] = make_int2(h, org[he_next_b(h)]);
+// Slots within a vertex's bucket come in any order: the tile ranks its
+// half-edges per vertex in LDS, reserves each vertex's run with one global
+// atomic, and places them (the match does not depend on the order).
+__global__ void __launch_bounds__(256) k_bucket(const int32_t *__restrict__ org, int nh,
+                                                const int32_t *__restrict__ vstart, int32_t *fill, int2 *bucket) {
+    __shared__ int s_hist[kHistBins];
+    __shared__ int s_lohi[2];
+    const int TB = 256 * kTileItems;
+    for (int base = blockIdx.x * TB; base < nh; base += gridDim.x * TB) {   // block-uniform
+        int v[kTileItems], w[kTileItems];
+        int vlo = 0x7fffffff, vhi = -1;
+#pragma unroll
+        for (int j = 0; j < kTileItems; j++) {
+            const int h = base + j * 256 + threadIdx.x;
+            v[j] = -1;
+            if (h < nh) {
+                v[j] = org[h];
+                w[j] = org[he_next_b(h)];
+                vlo = min(vlo, v[j]);
+                vhi = max(vhi, v[j]);
+            }
+        }
+        int lo, hi;
+        block_range(vlo, vhi, s_lohi, lo, hi);
+        if (hi >= lo && hi - lo < kHistBins) {   // block-uniform
+            const int range = hi - lo + 1;
+            for (int k = threadIdx.x; k < range; k += 256) s_hist[k] = 0;
+            __syncthreads();
+            int rank[kTileItems];
+#pragma unroll
+            for (int j = 0; j < kTileItems; j++) rank[j] = v[j] >= 0 ? atomicAdd(&s_hist[v[j] - lo], 1) : 0;
+            __syncthreads();
+            for (int k = threadIdx.x; k < range; k += 256) {
+                const int n = s_hist[k];
+                if (n) s_hist[k] = atomicAdd(&fill[lo + k], n);   // the run's first slot in the bucket
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kTileItems; j++)
+                if (v[j] >= 0)
+                    bucket[vstart[v[j]] + s_hist[v[j] - lo] + rank[j]] = make_int2(base + j * 256 + threadIdx.x, w[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kTileItems; j++)
+                if (v[j] >= 0)
+                    bucket[vstart[v[j]] + atomicAdd(&fill[v[j]], 1)] = make_int2(base + j * 256 + threadIdx.x, w[j]);
+        }
+        __syncthreads();   // the histogram and range are reused by the next tile
     }
 }
 
@@ -202,7 +306,7 @@ int32_t build_scan_tiles(int32_t n) {
 hipError_t launch_build_orient(const BuildBuffers &b, hipStream_t s) {
     hipLaunchKernelGGL(k_check_xy, dim3(grid_for(b.nv, 256)), dim3(256), 0, s, b.xy, b.nv, b.err_key);
     if (b.nt > 0)
-        hipLaunchKernelGGL(k_orient, dim3(grid_for(b.nt, 256)), dim3(256), 0, s, b.xy, b.tri, b.nv, b.nt,
+        hipLaunchKernelGGL(k_orient, dim3(grid_for(b.nt, 256 * kTileItems)), dim3(256), 0, s, b.xy, b.tri, b.nv, b.nt,
                            b.org, b.deg, b.err_key, b.nflipped);
     return hipGetLastError();
 }
@@ -213,7 +317,7 @@ hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s) {
                        b.scan_status, b.scan_ctr, b.err_key);
     long long nh = 3ll * b.nt;
     if (nh > 0) {
-        hipLaunchKernelGGL(k_bucket, dim3(grid_for(nh, 256)), dim3(256), 0, s, b.org, (int)nh, b.vstart,
+        hipLaunchKernelGGL(k_bucket, dim3(grid_for(nh, 256 * kTileItems)), dim3(256), 0, s, b.org, (int)nh, b.vstart,
                            b.fill, b.bucket);
         hipLaunchKernelGGL(k_match, dim3(grid_for(nh, 256)), dim3(256), 0, s, b.org, b.nt, b.vstart,
                            b.bucket, b.twin, b.err_key);
