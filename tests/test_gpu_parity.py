@@ -268,7 +268,11 @@ def test_launch_spec_roundtrip_and_errors():
 
 
 @pytest.mark.parametrize("spec", ["label=64x1,relink=64x1,compact=64x1,persist=64x1",
-                                  "label=1024x4,relink=128x8,compact=128x8,persist=1024x4096"])
+                                  "label=1024x4,relink=128x8,compact=128x8,persist=1024x4096",
+                                  # compaction tiles smaller than relink's: 8 per relink tile, and
+                                  # 384-triangle relink tiles straddling 256-triangle ones
+                                  "relink=256x4,compact=64x2",
+                                  "label=192x1,relink=192x2,compact=256x1,persist=192x100"])
 def test_launch_specs_do_not_change_results(spec):
     m = W.random_delaunay(20000, 41)
     o = oracle.polylla(m.xy, m.tri)
