@@ -197,7 +197,7 @@ def tips_and_middles_geometric(xy, org, twin, frontier):
 # invariants of an output (next', prev', seeds, loops)
 # --------------------------------------------------------------------------
 
-def check_output(xy, org, twin, next_o, prev_o, seeds, loop_off, loop_he, disk=True):
+def check_output(xy, org, twin, next_o, prev_o, seeds, loop_off, loop_he, disk=True, chi=None):
     """Asserts the structural invariants of a Polylla output and returns the
     per-triangle polygon labels and a few counts."""
     xy = np.asarray(xy, np.int64)
@@ -260,10 +260,36 @@ def check_output(xy, org, twin, next_o, prev_o, seeds, loop_off, loop_he, disk=T
     comp_area = np.zeros(len(owner), np.int64)
     np.add.at(comp_area, comp, tri_area)
     assert np.array_equal(loop_area, comp_area[first])
-    # Euler characteristic of the frontier graph of a disk: V - E + P = 1
+    # Euler characteristic of the frontier graph: V - E + P = 1 for a disk;
+    # chi, when given, for other domains (components minus holes)
     nedge = int(np.count_nonzero(onloop & ~inter) + np.count_nonzero(onloop & inter) // 2)
     nvert = len(np.unique(org))
-    if disk:
+    if chi is not None:
+        assert nvert - nedge + P == chi
+    elif disk:
         assert nvert - nedge + P == 1
     return {"comp": comp, "P": P, "Fh": len(loop_he), "E": nedge, "V": nvert,
             "total_area2": int(tri_area.sum()), "onloop": onloop}
+
+
+def grid_with_hole(n: int, seed: int, hole: int):
+    """A jittered n x n grid without its central hole x hole block of cells:
+    an annulus (Euler characteristic 0); the hole's vertices stay unused."""
+    from paper_2403_14723_amd import workloads as W
+    m = W.jittered_grid(n, seed=seed)
+    a = (n - hole) // 2
+    j, i = np.divmod(np.arange(n * n), n)
+    inside = (i >= a) & (i < a + hole) & (j >= a) & (j < a + hole)
+    keep = np.repeat(~inside, 2)   # cell (i, j) owns triangles 2*(j*n+i) and +1
+    return m.xy, np.ascontiguousarray(m.tri[keep]), 0
+
+
+def two_grids(n1: int, n2: int, seed: int):
+    """Two jittered grids side by side, sharing no vertex: two disks (Euler
+    characteristic 2)."""
+    from paper_2403_14723_amd import workloads as W
+    a, b = W.jittered_grid(n1, seed=seed), W.jittered_grid(n2, seed=seed + 1)
+    shift = np.array([W.DOMAIN + 4096, 0], np.int32)
+    xy = np.concatenate([a.xy, b.xy + shift]).astype(np.int32)
+    tri = np.concatenate([a.tri, b.tri + a.nv]).astype(np.int32)
+    return xy, tri, 2

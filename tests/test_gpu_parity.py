@@ -326,3 +326,13 @@ def test_flat_strip_every_triangle_a_polygon(ctx, n):
     m = W.flat_strip(n)
     g, o = check_case(ctx, m.xy, m.tri, m.name)
     assert o.stats["npoly"] == m.nt
+
+
+@pytest.mark.parametrize("case", ["hole", "two"])
+def test_hole_and_two_components(ctx, case):
+    """An inner boundary (a grid with a hole; its vertices unused) and two
+    disjoint components, against the oracle and the invariants."""
+    xy, tri, chi = pc.grid_with_hole(96, 17, 30) if case == "hole" else pc.two_grids(70, 45, 18)
+    g, o = check_case(ctx, xy, tri, case)
+    pc.check_output(xy, g["org"], g["twin"], g["next"], g["prev"], g["seeds"], g["loop_off"], g["loop_he"],
+                    chi=chi)

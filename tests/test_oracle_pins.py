@@ -257,3 +257,13 @@ def test_flat_strip_closed_form(n):
     np.testing.assert_array_equal(o.loop_he, h)
     np.testing.assert_array_equal(o.next, 3 * (h // 3) + (h % 3 + 1) % 3)
     np.testing.assert_array_equal(o.prev, 3 * (h // 3) + (h % 3 + 2) % 3)
+
+
+@pytest.mark.parametrize("case", ["hole", "two"])
+def test_hole_and_two_components(case):
+    """Domains that are not disks: a grid with a hole (an inner boundary
+    loop) and two disjoint grids.  Every structural invariant holds, with
+    V - E + P equal to the domain's Euler characteristic (0 and 2)."""
+    xy, tri, chi = pc.grid_with_hole(24, 7, 6) if case == "hole" else pc.two_grids(12, 17, 8)
+    o = oracle.polylla(xy, tri)
+    pc.check_output(xy, o.org, o.twin, o.next, o.prev, o.seeds, o.loop_off, o.loop_he, chi=chi)
