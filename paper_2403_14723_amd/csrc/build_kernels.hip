@@ -7,8 +7,9 @@
 //   k_scan_excl  exclusive scan of the out-degrees (decoupled look-back)
 //   k_bucket     half-edges grouped by origin vertex (CSR), each with its
 //                target vertex beside it
-//   k_match      twin(h) for h = u->v: the half-edge v->u in v's bucket; a
-//                second u->v in u's bucket, or two v->u, is non-manifold
+//   k_match      twin(h) for h = u->v: the half-edge v->u in v's bucket; two
+//                v->u, or (for an h with none) a second u->v in u's
+//                bucket, is non-manifold
 //
 // Errors are reduced with a 64-bit atomicMin over (rank << 8 | code) so the
 // reported code is deterministic: coordinate range first, then the lowest
@@ -280,9 +281,13 @@ __global__ void k_match(const int32_t *__restrict__ org, int nt, const int32_t *
                 ++nrev;
             }
         }
-        for (int k = vstart[u], e = vstart[u + 1]; k < e; k++) {
-            const int2 g = bucket[k];
-            if (g.x != h && g.y == v) ++ndup;
+        // a second u->v: when some v->u exists, its own search finds both
+        // u->v and reports them, so only a half-edge without a reverse looks
+        if (nrev == 0) {
+            for (int k = vstart[u], e = vstart[u + 1]; k < e; k++) {
+                const int2 g = bucket[k];
+                if (g.x != h && g.y == v) ++ndup;
+            }
         }
         if (nrev > 1 || ndup > 0) atomicMin(err, err_key(1ull + nt + h, -4));
         twin[h] = nrev == 1 ? found : -1;
