@@ -1348,20 +1348,30 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
     // 1. loop minima and lengths of this thread's ITEMS contiguous triangles;
     //    which loops are longer than a quad, and which of those k_walk stored
     //    (the rest k_emit writes)
+    //    (the walk-pool positions come with them, read whether or not a loop
+    //    was stored there, so a stored loop's pool read follows directly)
     uint8_t code[ITEMS], fl[ITEMS];
+    int lp[ITEMS];
+    const gcint lpos = (gcint)d.lpos;
     if (ITEMS == 4 && t0 + 4 <= nt) {
         const uint32_t w = *reinterpret_cast<GLOBAL const uint32_t *>(plb + t0);
         const uint32_t v = *reinterpret_cast<GLOBAL const uint32_t *>(tfl + t0);
+        const v4i l4 = *(GLOBAL const v4i *)(lpos + t0);
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             code[j] = (uint8_t)(w >> (8 * (j & 3)));
             fl[j] = (uint8_t)(v >> (8 * (j & 3)));
         }
+        lp[0] = l4.x;
+        lp[1 % ITEMS] = l4.y;
+        lp[2 % ITEMS] = l4.z;
+        lp[3 % ITEMS] = l4.w;
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             code[j] = t0 + j < nt ? plb[t0 + j] : 0;
             fl[j] = t0 + j < nt ? tfl[t0 + j] : 0;
+            lp[j] = t0 + j < nt ? lpos[t0 + j] : 0;
         }
     }
     int lens[ITEMS];
@@ -1465,7 +1475,7 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
                 // the loop begins at its minimum (loads first, all in flight)
                 static_assert(kWalkBuf % 4 == 0, "stored loops are read in 16-byte groups");
                 const int len = lens[j];
-                const GLOBAL v4i *src = (GLOBAL const v4i *)((gcint)wbuf + ((gcint)d.lpos)[t]);
+                const GLOBAL v4i *src = (GLOBAL const v4i *)((gcint)wbuf + lp[j]);
                 v4i g[kWalkBuf / 4 + 1];   // rotation index, then the half-edges
 #pragma unroll
                 for (int c = 0; c <= kWalkBuf / 4; c++) g[c] = src[c];
