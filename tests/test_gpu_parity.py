@@ -336,3 +336,17 @@ def test_hole_and_two_components(ctx, case):
     g, o = check_case(ctx, xy, tri, case)
     pc.check_output(xy, g["org"], g["twin"], g["next"], g["prev"], g["seeds"], g["loop_off"], g["loop_he"],
                     chi=chi)
+
+
+def test_pool_exhaustion_is_an_error_and_the_context_recovers():
+    """A context whose device pool is capped refuses a mesh that does not fit
+    with GP_ENOMEM (nothing is launched for it) and still meshes one that
+    does."""
+    big, small = W.jittered_grid(800, seed=3), W.jittered_grid(8, seed=3)
+    with gp.Context(0, pool_bytes=16 << 20) as c:
+        say("[gpu] capped pool: build that does not fit")
+        with pytest.raises(gp.GPolyllaError) as e:
+            c.build_halfedges(big.xy, big.tri)
+        assert e.value.code == gp.GP_ENOMEM
+        g = run_gpu(c, small.xy, small.tri, "after ENOMEM")
+    assert_parity(g, oracle.polylla(small.xy, small.tri), "after ENOMEM")
