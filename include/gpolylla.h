@@ -209,8 +209,10 @@ typedef struct {
 
 /*
  * Starts a server on the device of ctx (whose launch shapes it copies).  The
- * server owns its own streams and device memory: n_lanes arenas of
- * pool_bytes / n_lanes each.  A request is admitted into a batch when the
+ * server owns its own streams, threads and device memory: n_lanes lanes,
+ * each with a stream, a host thread and an arena of pool_bytes / n_lanes
+ * bytes.  Submitted inputs are copied into host buffers that the server
+ * reuses after requests complete.  A request is admitted into a batch when the
  * exact device footprint of the batch (every half-edge build plus the
  * batched meshing run) fits a lane's arena.  Batches on different lanes
  * overlap; requests that arrive while batches run join the next free lane
