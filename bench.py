@@ -27,6 +27,7 @@ WORKLOADS = {
     "plain_4096x4096_warped": "plain_large_warped",
     "plain_1024x1024": "plain_scale",
     "plain_32x32": "plain_small",
+    "delaunay1000000_s21m": "delaunay_1m",
 }
 
 
@@ -52,14 +53,14 @@ def kernel_bytes(name, nt, nv, npoly, nloop):
     }.get(name)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated), when the summary was taken on the
-    kernel sources as they are now; else None."""
+def measured_traffic(kernel, workload="plain_4096x4096_warped"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of
+    `workload` (FETCH_SIZE + WRITE_SIZE, calibrated), when the summary was
+    taken on the kernel sources as they are now; else None."""
     from paper_2403_14723_amd import prof
     here = os.path.dirname(os.path.abspath(__file__))
     sha = prof.sources_sha256()
-    for path in sorted(glob.glob(os.path.join(here, "profiles", "*.md"))):
+    for path in sorted(glob.glob(os.path.join(here, "profiles", f"*_{workload}.md"))):
         with open(path) as f:
             rec = prof.traffic_line(f.read())
         if rec and rec.get("kernel") == kernel and rec.get("sources_sha256") == sha:
@@ -238,7 +239,7 @@ def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
     triangulation of random points, numbered along a Z-order curve, meshed on
     the device like the plain workload (graph replay)."""
     t0 = time.perf_counter()
-    m = W.random_delaunay(npts, seed=21, order="morton")
+    m = W.delaunay_1m() if npts == 1_000_000 else W.random_delaunay(npts, seed=21, order="morton")
     gen_s = time.perf_counter() - t0
     out = _graph_form(gp, stream, m, steps)
     out["generate_s"] = round(gen_s, 1)
@@ -445,7 +446,7 @@ def main():
     dom_bytes = kernel_bytes(dom, nt, nv, P, Fh)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     value = nt / (ms_per_step * 1e-3) / 1e6
-    traffic, traffic_src = measured_traffic(dom.split("<")[0])
+    traffic, traffic_src = measured_traffic(dom.split("<")[0], mesh.name)
 
     batched = served = delaunay = transfers = band = None
     if not args.no_forms:

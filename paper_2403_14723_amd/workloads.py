@@ -223,6 +223,12 @@ def plain_scale() -> Mesh:
     return jittered_grid(1024, seed=1, name="plain_1024x1024")
 
 
+def delaunay_1m() -> Mesh:
+    """Delaunay triangulation of 1M seeded random points, numbered along a
+    Z-order curve: the general-position workload (1,979,675 triangles)."""
+    return random_delaunay(1_000_000, 21, order="morton")
+
+
 def plain_large_warped() -> Mesh:
     """4096 x 4096 cells with the Gaussian-bump warp: 33,554,432 triangles."""
     return jittered_grid(4096, seed=2, warp=True, name="plain_4096x4096_warped")
