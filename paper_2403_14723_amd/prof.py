@@ -7,9 +7,9 @@ Usage (after the profiling runs on a GPU host):
 
 Counter scale: rocprofv3 reports FETCH_SIZE and WRITE_SIZE in KiB per dispatch,
 and on this device FETCH_SIZE counts half of the bytes a plain copy kernel
-reads.  Both are calibrated on the largest device-to-device copy of the run
-(the half-edge build's copy of the triangle array, 12*T bytes read and
-written), and the calibrated bytes per launch are written into the summary
+reads.  Both are calibrated on the largest copy kernel of the profiled run,
+which moves 12*T bytes (the size of the triangle array and of each of next'
+and prev'), and the calibrated bytes per launch are written into the summary
 with a hash of the kernel sources, so bench.py can tell whether the counters
 still describe the kernels it runs.
 """
@@ -97,7 +97,7 @@ def main():
     for name, calls, avg, pct in sorted(read_stats(a.stats), key=lambda r: -r[3]):
         lines.append(f"| {name} | {calls} | {avg:.2f} | {pct:.2f} |")
     lines += ["", "## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE)", "",
-              f"Calibration on the largest device copy (the build's copy of tri, {copy_bytes:,} B read and "
+              f"Calibration on the largest copy kernel ({copy_bytes:,} B read and "
               f"written): FETCH_SIZE x {f_scale:.3f}, WRITE_SIZE x {w_scale:.3f} (KiB -> bytes).", "",
               "| kernel | dispatches | fetch MB | write MB |", "|---|---|---|---|"]
     rec = None
