@@ -231,7 +231,8 @@ int gpolylla_serve_submit(gp_server *srv, const int32_t *xy, int32_t nv, const i
  * ticket can be waited for once.  Thread-safe. */
 int gpolylla_serve_wait(gp_server *srv, uint64_t ticket, int32_t timeout_ms, gp_result **out);
 int gpolylla_serve_stats(gp_server *srv, gp_serve_stats *stats);
-/* Clears the latency and throughput statistics (after a warm-up). */
+/* Clears the latency and throughput statistics (after a warm-up).  Requests
+ * not finished yet count as submitted afterwards. */
 int gpolylla_serve_reset_stats(gp_server *srv);
 /* Finishes every queued request, then stops.  Results already handed out
  * stay valid until freed. */

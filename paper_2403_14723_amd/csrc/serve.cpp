@@ -486,7 +486,11 @@ int gpolylla_serve_reset_stats(gp_server *s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->lat_ms.clear();
     s->completed = s->failed = s->rejected = s->batches = s->tri_done = 0;
-    s->submitted = (int64_t)(s->queue.size());
+    // requests not finished yet (queued or on a lane) count as submitted, so
+    // that in_flight stays exact as they complete
+    int64_t pending = 0;
+    for (const auto &kv : s->reqs) pending += kv.second->done ? 0 : 1;
+    s->submitted = pending;
     s->have_first = false;
     return GP_OK;
 }

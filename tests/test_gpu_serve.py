@@ -109,3 +109,22 @@ def test_stop_drains_requests_in_flight(ctx):
     st = srv.stats()
     assert st["submitted"] == 1 + 4 * len(reqs)
     srv.stop()   # returns once every lane has drained the queue
+
+
+def test_reset_stats_with_requests_in_flight(ctx):
+    """Statistics cleared while requests are queued or on a lane: those
+    requests count as submitted afterwards, so once all are waited for,
+    every one of them is completed and none is in flight."""
+    reqs = [W.jittered_grid(n, seed=700 + n, warp=True) for n in (60, 120, 180, 240)]
+    with gp.Server(ctx, pool_bytes=1 << 30, max_batch=2, n_lanes=2) as srv:
+        say("[gpu] serve: reset_stats with requests in flight")
+        tickets = [srv.submit(m.xy, m.tri) for m in reqs * 3]
+        srv.reset_stats()
+        mid = srv.stats()
+        assert 0 <= mid["in_flight"] <= len(tickets)
+        for t in tickets:
+            srv.wait(t, 60000).free()
+        st = srv.stats()
+        assert st["failed"] == 0
+        assert st["in_flight"] == 0
+        assert st["completed"] == st["submitted"] == mid["in_flight"] + mid["completed"]
