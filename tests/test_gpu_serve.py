@@ -128,3 +128,37 @@ def test_reset_stats_with_requests_in_flight(ctx):
         assert st["failed"] == 0
         assert st["in_flight"] == 0
         assert st["completed"] == st["submitted"] == mid["in_flight"] + mid["completed"]
+
+
+def test_queue_full_and_wait_timeout(ctx):
+    """A full queue rejects a request with GP_EAGAIN and counts it; a wait
+    that times out returns GP_ETIMEDOUT and leaves the ticket valid.  One lane
+    and a queue of one: while the lane meshes a 2M-triangle request (a few
+    milliseconds), tiny requests submitted back to back fill the queue."""
+    big = W.jittered_grid(1024, seed=11)
+    small = W.jittered_grid(6, seed=12)
+    o = oracle.polylla(small.xy, small.tri)
+    with gp.Server(ctx, pool_bytes=1 << 30, max_batch=1, max_queue=1, n_lanes=1) as srv:
+        say("[gpu] serve: wait timeout and full queue")
+        tb = srv.submit(big.xy, big.tri)
+        with pytest.raises(gp.GPolyllaError) as e:
+            srv.wait(tb, 0)
+        assert e.value.code == gp.GP_ETIMEDOUT
+        accepted, again = [], 0
+        for _ in range(6):
+            try:
+                accepted.append(srv.submit(small.xy, small.tri))
+            except gp.GPolyllaError as err:
+                assert err.code == gp.GP_EAGAIN
+                again += 1
+        assert again >= 1
+        r = srv.wait(tb, 60000)   # the ticket survived the timed-out wait
+        assert r.info()["nt"] == big.nt
+        r.free()
+        for t in accepted:
+            r = srv.wait(t, 60000)
+            assert np.array_equal(r.copy()["loop_he"], o.loop_he)
+            r.free()
+        st = srv.stats()
+        assert st["rejected"] == again
+        assert st["completed"] == 1 + len(accepted) and st["failed"] == 0
