@@ -58,7 +58,9 @@ extern "C" {
 #define GP_ETOOBIG (-8)       /* request footprint exceeds the server pool */
 #define GP_ETIMEDOUT (-9)     /* wait timed out */
 #define GP_ECORRUPT (-10)     /* a rotation, walk or scan guard tripped: the half-edge
-                                 structure is not a valid manifold triangulation */
+                                 structure is not a valid manifold triangulation, or
+                                 a turn around one vertex passed more than 2^20 edges
+                                 (a vertex of that degree is beyond the supported range) */
 
 /* ---- flags -------------------------------------------------------------- */
 #define GP_IN_DEVICE 0x1u     /* build: xy and tri are device pointers on the context's device */
