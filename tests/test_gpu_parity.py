@@ -124,10 +124,31 @@ def test_delaunay_large(ctx):
 
 def test_plain_large_warped_full(ctx):
     """The 33.5M-triangle workload at full size, default launch configuration
-    (the one the benchmark times), every output element compared."""
+    (the one the benchmark times), every output element compared; then the
+    benchmark's band form of it (band 3 of 8 row bands, two halo rows) against
+    the oracle, and its band proper against the whole mesh."""
     m = W.plain_large_warped()
     g, o = check_case(ctx, m.xy, m.tri, m.name)
     assert o.stats["ntips"] > 0
+    del o
+    n, nb, b = 4096, 8, 3
+    rows = n // nb
+    bm = W.grid_band(m, n, b, nb)
+    gb, _ = check_case(ctx, bm.xy, bm.tri, bm.name)
+    off = 6 * n * (b * rows - 2)
+    lo, hi = 6 * n * b * rows - off, 6 * n * (b + 1) * rows - off
+    for key in ("next", "prev"):
+        got = gb[key][lo:hi]
+        np.testing.assert_array_equal(np.where(got >= 0, got + off, -1), g[key][lo + off:hi + off])
+
+
+def test_delaunay_1m_workload(ctx):
+    """The benchmark's general-position workload at full size (1M random
+    points, Z-order numbering, 1,979,675 triangles), every element compared."""
+    m = W.delaunay_1m()
+    assert m.nt == 1979675
+    g, o = check_case(ctx, m.xy, m.tri, m.name)
+    assert o.stats["ntips"] > 10000
 
 
 def test_batch_equals_plain(ctx):
