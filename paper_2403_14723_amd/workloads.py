@@ -46,7 +46,7 @@ _MIX1 = np.uint64(0xBF58476D1CE4E5B9)
 _MIX2 = np.uint64(0x94D049BB133111EB)
 
 # stream tags: each kind of draw has its own counter space
-_S_JX, _S_JY, _S_DIAG, _S_WARP, _S_MESH, _S_REQ, _S_PTS = 1, 2, 3, 4, 5, 6, 7
+_S_JX, _S_JY, _S_DIAG, _S_WARP, _S_MESH, _S_REQ, _S_PTS, _S_SCR = 1, 2, 3, 4, 5, 6, 7, 8
 
 
 def splitmix64(x: np.ndarray) -> np.ndarray:
@@ -207,6 +207,27 @@ def flat_strip(n: int, name: str = "") -> Mesh:
     tri[0::2] = up
     tri[1::2] = down
     return Mesh(np.ascontiguousarray(xy), np.ascontiguousarray(tri.astype(np.int32)), name or f"flat_strip{n}")
+
+
+def scrambled(m: Mesh, seed: int) -> Mesh:
+    """The same triangulation numbered at random: vertices and triangles in a
+    seeded random order, each triangle's corners rotated by a random shift,
+    and about half of the triangles listed clockwise.  Neighbours then
+    rarely share a tile, vertex ids in a tile span the whole range, and equal
+    lengths are broken among scattered half-edge ids."""
+    nv, nt = m.nv, m.nt
+    ids = lambda lo, n: np.arange(lo, lo + n, dtype=np.uint64)
+    vperm = np.argsort(uniform01(seed, _S_SCR, ids(0, nv)), kind="stable")   # new id -> old vertex
+    rank = np.empty(nv, np.int64)
+    rank[vperm] = np.arange(nv)
+    tperm = np.argsort(uniform01(seed, _S_SCR, ids(nv, nt)), kind="stable")
+    tri = rank[m.tri[tperm].astype(np.int64)]
+    rot = uniform_int(seed, _S_SCR, ids(nv + nt, nt), 0, 2)
+    tri = np.take_along_axis(tri, (np.arange(3)[None, :] + rot[:, None]) % 3, axis=1)
+    cw = uniform_int(seed, _S_SCR, ids(nv + 2 * nt, nt), 0, 1).astype(bool)
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    return Mesh(np.ascontiguousarray(m.xy[vperm]), np.ascontiguousarray(tri.astype(np.int32)),
+                f"{m.name}_scr{seed}")
 
 
 # ---------------------------------------------------------------------------

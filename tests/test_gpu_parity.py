@@ -340,6 +340,33 @@ def test_grid_bands(ctx):
             np.testing.assert_array_equal(np.where(got >= 0, got + off, -1), whole[key][lo + off:hi + off])
 
 
+def _tall_strip(n):
+    """flat_strip stretched 8x upwards: in every triangle the two slanted
+    sides are the longest edges, and exactly equal when the base width
+    2^20 // n is even, so that every label is a tie."""
+    assert ((1 << 20) // n) % 2 == 0
+    m = W.flat_strip(n)
+    xy = m.xy.copy()
+    xy[:, 1] *= 8
+    return W.Mesh(xy, m.tri, f"tall_strip{n}")
+
+
+SCRAMBLED = [W.scrambled(W.jittered_grid(96, seed=5, warp=True), 1),
+             W.scrambled(_tall_strip(1000), 2),
+             W.scrambled(W.random_delaunay(20000, 8), 3),
+             W.scrambled(W.flat_strip(1500), 4)]
+
+
+@pytest.mark.parametrize("mesh", SCRAMBLED, ids=[m.name for m in SCRAMBLED])
+def test_scrambled_numbering(ctx, mesh):
+    """Random vertex and triangle order, rotated corners, mixed orientation:
+    most neighbours lie in other tiles, and ties fall among scattered ids."""
+    g, o = check_case(ctx, mesh.xy, mesh.tri, mesh.name)
+    assert g["nflipped"] > 0
+    if mesh.name.startswith("tall_strip"):
+        assert o.stats["nties"] == mesh.nt
+
+
 @pytest.mark.parametrize("n", [600, 5000])
 def test_flat_strip_every_triangle_a_polygon(ctx, n):
     """Three loop half-edges per triangle, more than a compaction tile keeps

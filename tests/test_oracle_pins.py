@@ -267,3 +267,19 @@ def test_hole_and_two_components(case):
     xy, tri, chi = pc.grid_with_hole(24, 7, 6) if case == "hole" else pc.two_grids(12, 17, 8)
     o = oracle.polylla(xy, tri)
     pc.check_output(xy, o.org, o.twin, o.next, o.prev, o.seeds, o.loop_off, o.loop_he, chi=chi)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_scrambled_is_the_same_triangulation(seed):
+    """The scrambling input generator keeps the triangulation: the same
+    triangles as sets of points, and on a tie-free mesh the oracle finds as
+    many polygons, with every structural invariant intact."""
+    m = W.random_delaunay(1500, 60 + seed)
+    s = W.scrambled(m, seed)
+    assert s.nv == m.nv and s.nt == m.nt
+    key = lambda xy, tri: sorted(tuple(sorted(map(tuple, xy[t].tolist()))) for t in tri)
+    assert key(m.xy, m.tri) == key(s.xy, s.tri)
+    a, b = oracle.polylla(m.xy, m.tri), oracle.polylla(s.xy, s.tri)
+    assert a.stats["nties"] == 0 and 0 < b.stats["nflipped"] < s.nt
+    assert b.stats["npoly"] == a.stats["npoly"] and b.stats["nloop_he"] == a.stats["nloop_he"]
+    pc.check_output(s.xy, b.org, b.twin, b.next, b.prev, b.seeds, b.loop_off, b.loop_he)
