@@ -149,6 +149,11 @@ int gpolylla_ctx_get_launch(const gp_ctx *ctx, char *buf, int32_t cap);
  * success *out is a device-resident mesh owned by the caller (free it with
  * gpolylla_mesh_free).  Errors: GP_EINVAL, GP_ERANGE, GP_EDEGEN,
  * GP_ENONMANIFOLD, GP_ENOMEM, GP_EHIP.  Synchronous.
+ * Numbering is kept as given, and the meshing kernels are fastest when it is
+ * spatially coherent (grid rows, a space-filling curve): neighbours then
+ * share cache lines and tiles.  A randomly numbered 33.5M-triangle grid
+ * meshes about 9x slower than the same grid numbered by rows; results are
+ * the same either way, up to ties, which the numbering breaks.
  */
 int gpolylla_build_halfedges(gp_ctx *ctx, const int32_t *xy, int32_t nv, const int32_t *tri,
                              int32_t nt, uint32_t flags, gp_mesh **out);
