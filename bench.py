@@ -258,9 +258,12 @@ def bench_band(gp, W, stream, mesh, steps, nbands=8, band=3):
     return out
 
 
-def bench_served(gp, W, n_req=2000, warm=64, cap_n=256, rhos=(0.5, 0.8)):
+def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8)):
     """Continuous-batching server: capacity from a closed loop, then Poisson
-    arrivals at rho * capacity; latency = submit -> result on the host."""
+    arrivals at rho * capacity; latency = submit -> result on the host.  The
+    warm-up closed loop is as large as the capacity run, so that the server's
+    input pool already holds a buffer for every request in flight (a steady
+    state server's pool does)."""
     import queue
     import threading
     import numpy as np
