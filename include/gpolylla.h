@@ -199,6 +199,47 @@ void gpolylla_result_free(gp_result *res);
 /* Waits until all queued work of the context has finished. */
 int gpolylla_ctx_sync(gp_ctx *ctx);
 
+/* ---- meshing without allocation ----------------------------------------- */
+
+/* Counts of one gpolylla_mesh_noalloc run, written by the device when the run
+ * completes (the same counts gpolylla_result_info reports). */
+typedef struct {
+    int32_t status;       /* GP_OK, or GP_ECORRUPT when a device guard tripped */
+    int32_t npoly;        /* polygons (= seeds) */
+    int32_t nloop_he;     /* half-edges on loops */
+    int32_t ntips;        /* barrier tips repaired */
+    int32_t nmiddle;      /* distinct middle edges added by the repair */
+    int32_t nties;        /* triangles whose largest squared length is shared */
+    int32_t reserved[2];  /* written as 0 */
+} gp_dev_counts;
+
+/* Size of the library's per-device scratch array for gpolylla_mesh_noalloc. */
+#define GP_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * For callers that cannot allocate: code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc.  The same meshing run as
+ * gpolylla_mesh (the same kernels, results identical element by element), with
+ * no device, pinned-host or pool allocation and no host synchronisation: it
+ * returns once the run is queued on the context's stream.
+ *   mesh:   built beforehand by gpolylla_build_halfedges on this context
+ *   out:    caller-allocated device buffers on the context's device, at least
+ *           next, prev: 3*nt + 1 int32; seeds: nt + 1; loop_off: nt + 2;
+ *           loop_he: 3*nt + 1 (the entries past the counts are scratch)
+ *   counts: caller-allocated device memory; receives the counts of the run
+ * The run's scratch (labels, lists, per-tile totals) lives in one static
+ * array of GP_NOALLOC_SCRATCH_BYTES per device, set up by gpolylla_ctx_create
+ * and held until the process ends; a mesh whose scratch does not fit (about
+ * four million triangles with the default launch shapes) is refused with
+ * GP_ETOOBIG before anything is queued.  Every call on one device shares
+ * that array: calls on one context are ordered by its stream, and calls that
+ * overlap on one device (other contexts or streams) race and must not be made.
+ * Errors: GP_EINVAL (null argument, mesh of another context), GP_ETOOBIG,
+ * GP_EHIP (the scratch array could not be located at set-up, or a launch
+ * failed).  Errors found by the kernels arrive in counts->status.
+ */
+int gpolylla_mesh_noalloc(gp_ctx *ctx, const gp_mesh *mesh, const gp_result_dev *out, gp_dev_counts *counts);
+
 /* ---- serving ------------------------------------------------------------ */
 
 typedef struct {

@@ -61,6 +61,14 @@ class gp_result_dev(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("next", "prev", "seeds", "loop_off", "loop_he")]
 
 
+class gp_dev_counts(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("status", "npoly", "nloop_he", "ntips", "nmiddle", "nties",
+                                              "reserved0", "reserved1")]
+
+
+GP_NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -106,6 +114,7 @@ def _load():
         "gpolylla_result_copy": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
         "gpolylla_result_device": (ctypes.c_int, [_P, ctypes.POINTER(gp_result_dev)]),
         "gpolylla_result_free": (None, [_P]),
+        "gpolylla_mesh_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(gp_result_dev), _P]),
         "gpolylla_serve_start": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_opts), ctypes.POINTER(_P)]),
         "gpolylla_serve_submit": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_uint64)]),
@@ -136,7 +145,7 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_ctx_set_launch", "gpolylla_ctx_get_launch",
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
-            "gpolylla_result_device", "gpolylla_result_free", "gpolylla_serve_start", "gpolylla_serve_submit",
+            "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_serve_start", "gpolylla_serve_submit",
             "gpolylla_serve_wait", "gpolylla_serve_stats", "gpolylla_serve_reset_stats", "gpolylla_serve_stop"]
 
 
@@ -283,6 +292,12 @@ def gpolylla_result_device(res) -> dict:
 
 def gpolylla_result_free(res):
     _load().gpolylla_result_free(res)
+
+
+def gpolylla_mesh_noalloc(ctx, mesh, out: gp_result_dev, counts_ptr: int) -> int:
+    """Queues a meshing run into caller-allocated device buffers (out, and
+    counts_ptr: device memory for a gp_dev_counts); returns the C status."""
+    return _load().gpolylla_mesh_noalloc(ctx, mesh, ctypes.byref(out), ctypes.c_void_p(counts_ptr))
 
 
 def gpolylla_serve_start(ctx, opts: gp_serve_opts | None = None):

@@ -150,6 +150,13 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
 // be coherent pinned host memory.
 hipError_t launch_copy_words(void *dst, const void *src, size_t bytes, hipStream_t s);
 
+// Writes one descriptor into device memory with a kernel (its value travels
+// as a kernel argument), so no host staging buffer is needed.
+hipError_t launch_put_desc(const MeshDesc &d, MeshDesc *dst, hipStream_t s);
+// Writes the counts of mesh counters c as 8 int32: status (0 or -10), npoly,
+// nloop, ntips, nmiddle, nties, 0, 0.
+hipError_t launch_export_counts(const MeshCounters *c, int32_t *out, hipStream_t s);
+
 // tiles of one mesh for a given tile size; every mesh has at least one tile
 // so that an empty mesh still gets its loop_off[0] written
 inline int32_t tiles_for(int64_t n, int64_t tile) {

@@ -1566,6 +1566,34 @@ hipError_t launch_copy_words(void *dst, const void *src, size_t bytes, hipStream
     return hipGetLastError();
 }
 
+__global__ void k_put_desc(MeshDesc d, MeshDesc *dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
+hipError_t launch_put_desc(const MeshDesc &d, MeshDesc *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_export_counts(const MeshCounters *c, int32_t *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const MeshCounters k = *c;
+        out[0] = k.err ? -10 : 0;   // GP_ECORRUPT
+        out[1] = k.npoly;
+        out[2] = k.nloop;
+        out[3] = k.ntips;
+        out[4] = k.nmiddle;
+        out[5] = k.nties;
+        out[6] = 0;
+        out[7] = 0;
+    }
+}
+
+hipError_t launch_export_counts(const MeshCounters *c, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_export_counts, dim3(1), dim3(64), 0, s, c, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // host launch of the whole chain
 // ---------------------------------------------------------------------------

@@ -196,39 +196,42 @@ void run_unref(RunState *r) {
 
 namespace {
 
-struct Plan {
-    std::vector<gp::MeshDesc> descs;   // sizes and tile offsets filled in
-    std::vector<int32_t> nts;
+// Sizes of one run over meshes of nts[0..n) triangles.  No allocation: the
+// no-allocation entry point plans its single mesh with this directly.
+struct PlanSizes {
     int64_t tri_tiles = 0, he_tiles = 0, cmp_tiles = 0, cap_tips = 0, cap_fix = 0;
     int64_t walk_cap = 0, emit_cap = 0, wbuf_cap = 0;
     size_t out_bytes = 0, tmp_bytes = 0, tmp_mesh = 0;
 };
 
-int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Plan *p) {
+// Fills the sizes and tile offsets of descs[0..n) (nt, nv, *_tile0) and *p.
+int plan_core(const gp::LaunchCfg &cfg, const int32_t *nts, const int32_t *nvs, int n, gp::MeshDesc *descs,
+              PlanSizes *p) {
     const int64_t tt = (int64_t)cfg.block_label * cfg.items_label;
     const int64_t th = (int64_t)cfg.block_relink * cfg.items_relink;
     const int64_t tc = (int64_t)cfg.block_compact * cfg.items_compact;
-    p->descs.assign(n, gp::MeshDesc{});
-    p->nts.resize(n);
+    *p = PlanSizes{};
+    int64_t total_nt = 0;
     for (int i = 0; i < n; i++) {
-        const gp_mesh *m = meshes[i];
-        gp::MeshDesc &d = p->descs[i];
-        d.nt = m->nt;
-        d.nv = m->nv;
+        const int32_t nt = nts[i];
+        gp::MeshDesc &d = descs[i];
+        d = gp::MeshDesc{};
+        d.nt = nt;
+        d.nv = nvs ? nvs[i] : 0;
         d.tri_tile0 = (int32_t)p->tri_tiles;
         d.he_tile0 = (int32_t)p->he_tiles;
         d.cmp_tile0 = (int32_t)p->cmp_tiles;
-        p->nts[i] = m->nt;
-        p->tri_tiles += gp::tiles_for(m->nt, tt);
-        p->he_tiles += gp::tiles_for(m->nt, th);
-        p->cmp_tiles += gp::tiles_for(m->nt, tc);
-        p->cap_tips += m->nt / 2 + 2;   // tips are interior vertices: at most T/2 + 1
-        const int64_t nh = 3ll * m->nt;
-        p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(m->nt + 1) +
-                        arena_bytes<int32_t>(m->nt + 2);
-        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(m->nt + 4, 4)) + arena_bytes<int32_t>(m->nt + 1);
+        p->tri_tiles += gp::tiles_for(nt, tt);
+        p->he_tiles += gp::tiles_for(nt, th);
+        p->cmp_tiles += gp::tiles_for(nt, tc);
+        p->cap_tips += nt / 2 + 2;   // tips are interior vertices: at most T/2 + 1
+        const int64_t nh = 3ll * nt;
+        p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(nt + 1) +
+                        arena_bytes<int32_t>(nt + 2);
+        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(nt + 4, 4)) + arena_bytes<int32_t>(nt + 1);
+        total_nt += nt;
+        if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
     }
-    if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
     p->cap_fix = 2 * p->cap_tips;
     // striped lists, sized for the worst case: every triangle of a tile holds
     // a seed (walk) or a loop minimum (emit); repair seeds spread evenly
@@ -237,8 +240,6 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
     p->emit_cap = (p->cmp_tiles + S - 1) / S * tc;
     // walked loops: at most 3T half-edges in all (each loop is stored once)
     // plus one rotation index per loop; slack for uneven stripes
-    int64_t total_nt = 0;
-    for (int i = 0; i < n; i++) total_nt += meshes[i]->nt;
     p->wbuf_cap = align_up((4 * total_nt + S - 1) / S + 4096, 4);
     if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff || p->wbuf_cap * S > 0x7fffffff)
         return GP_ERANGE;
@@ -250,9 +251,27 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
     return GP_OK;
 }
 
-void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp::RunBuffers *rb,
+struct Plan : PlanSizes {
+    std::vector<gp::MeshDesc> descs;   // sizes and tile offsets filled in
+    std::vector<int32_t> nts;
+};
+
+int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Plan *p) {
+    p->descs.assign(n, gp::MeshDesc{});
+    p->nts.resize(n);
+    std::vector<int32_t> nvs(n);
+    for (int i = 0; i < n; i++) {
+        p->nts[i] = meshes[i]->nt;
+        nvs[i] = meshes[i]->nv;
+    }
+    return plan_core(cfg, p->nts.data(), nvs.data(), n, p->descs.data(), p);
+}
+
+// Carves the run scratch out of `block` (PlanSizes::tmp_bytes bytes): the
+// run's buffers into *rb, each mesh's label, loop and walk-position arrays
+// into tflag[i], pl[i], lpos[i].  descs holds the planned tile offsets.
+void layout_scratch(const PlanSizes &p, const gp::MeshDesc *descs, int n, void *block, gp::RunBuffers *rb,
                     uint8_t **tflag, uint8_t **pl, int32_t **lpos) {
-    const int n = (int)p.descs.size();
     const int64_t S = gp::kStripes;
     Arena at{static_cast<char *>(block), p.tmp_bytes, 0};
     *rb = gp::RunBuffers{};
@@ -270,11 +289,10 @@ void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp
     rb->status = at.take<uint64_t>(p.cmp_tiles);
     rb->cpre = at.take<uint64_t>(p.cmp_tiles);
     {
-        const int64_t tc = (int64_t)p.cmp_tiles;   // (tiles of each mesh are in descs)
         int64_t mc = 1;
         for (int i = 0; i < n; i++) {
-            const int64_t end = i + 1 < n ? p.descs[i + 1].cmp_tile0 : tc;
-            const int64_t nt_tiles = end - p.descs[i].cmp_tile0;
+            const int64_t end = i + 1 < n ? descs[i + 1].cmp_tile0 : p.cmp_tiles;
+            const int64_t nt_tiles = end - descs[i].cmp_tile0;
             mc = std::max<int64_t>(mc, (nt_tiles + gp::kScanChunk - 1) / gp::kScanChunk);
         }
         rb->max_chunks = (int32_t)mc;
@@ -289,9 +307,9 @@ void layout_scratch(const Plan &p, void *block, const gp_mesh *const *meshes, gp
     rb->wbuf_counts = at.take<int32_t>(S * gp::kStripePad);
     rb->wbuf_cap = (int32_t)p.wbuf_cap;
     for (int i = 0; i < n; i++) {
-        tflag[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));
-        pl[i] = at.take<uint8_t>(align_up(meshes[i]->nt + 4, 4));   // whole words: k_walk claims by OR
-        lpos[i] = at.take<int32_t>(meshes[i]->nt + 1);
+        tflag[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));
+        pl[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));   // whole words: k_walk claims by OR
+        lpos[i] = at.take<int32_t>(descs[i].nt + 1);
     }
 }
 
@@ -310,14 +328,9 @@ size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device) {
 }
 
 size_t batch_footprint(const gp::LaunchCfg &cfg, const int32_t *nts, int n) {
-    std::vector<gp_mesh> shapes(n);
-    std::vector<const gp_mesh *> ptrs(n);
-    for (int i = 0; i < n; i++) {
-        shapes[i].nt = nts[i];
-        ptrs[i] = &shapes[i];
-    }
-    Plan p;
-    if (make_plan(cfg, ptrs.data(), n, &p) != GP_OK) return (size_t)-1;
+    std::vector<gp::MeshDesc> descs(n);
+    PlanSizes p;
+    if (plan_core(cfg, nts, nullptr, n, descs.data(), &p) != GP_OK) return (size_t)-1;
     return align_up(p.out_bytes) + align_up(p.tmp_bytes);
 }
 
@@ -388,14 +401,7 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     e.tflag.resize(n);
     e.pl.resize(n);
     e.lpos.resize(n);
-    // layout_scratch only needs the sizes of the meshes
-    std::vector<gp_mesh> shapes(n);
-    std::vector<const gp_mesh *> ptrs(n);
-    for (int i = 0; i < n; i++) {
-        shapes[i].nt = plan.nts[i];
-        ptrs[i] = &shapes[i];
-    }
-    layout_scratch(plan, e.scratch, ptrs.data(), &e.rb, e.tflag.data(), e.pl.data(), e.lpos.data());
+    layout_scratch(plan, plan.descs.data(), n, e.scratch, &e.rb, e.tflag.data(), e.pl.data(), e.lpos.data());
     hipGraph_t graph = nullptr;
     hipStream_t s = c->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -417,6 +423,48 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     gc.entries.push_back(std::move(e));
     *out = &gc.entries.back();
     return GP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// scratch of gpolylla_mesh_noalloc: one static array per device
+//
+// In host code `scratch` names a host-side stand-in, not device memory; its
+// device address is looked up once per device with hipGetSymbolAddress (at
+// context creation, with the device current) and only that address is ever
+// handed to kernels.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) char scratch[GP_NOALLOC_SCRATCH_BYTES];
+static_assert(sizeof(gp_dev_counts) == 8 * sizeof(int32_t), "the counts kernel writes 8 int32");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Called with `device` current.  A failed lookup leaves the pointer null:
+// contexts still work, gpolylla_mesh_noalloc then answers GP_EHIP.
+void noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_tried[device]) return;
+    g_scratch_tried[device] = true;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 }  // namespace
@@ -512,6 +560,7 @@ int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
     if (!c) return GP_ENOMEM;
     c->device = device;
     DeviceGuard g(device);
+    noalloc_setup(device);
     if (opts) {
         c->pool.cap = opts->pool_bytes;
         c->profile = opts->profile != 0;
@@ -812,7 +861,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         pl = ge->pl;
         lpos = ge->lpos;
     } else {
-        layout_scratch(plan, p_tmp, meshes, &rb, tflag.data(), pl.data(), lpos.data());
+        layout_scratch(plan, plan.descs.data(), n, p_tmp, &rb, tflag.data(), pl.data(), lpos.data());
     }
     Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
     std::vector<gp_result *> res(n, nullptr);
@@ -914,6 +963,46 @@ GraphCache &graphs_of(gp_ctx *c) {
 int gpolylla_mesh(gp_ctx *c, const gp_mesh *m, uint32_t out_flags, gp_result **out) {
     if (!m) return GP_EINVAL;
     return gpolylla_mesh_batch(c, &m, 1, out_flags, out);
+}
+
+int gpolylla_mesh_noalloc(gp_ctx *c, const gp_mesh *m, const gp_result_dev *out, gp_dev_counts *counts) {
+    if (!c || !m || !out || !counts || m->ctx != c) return GP_EINVAL;
+    if (!out->next || !out->prev || !out->seeds || !out->loop_off || !out->loop_he) return GP_EINVAL;
+    void *base = noalloc_scratch(c->device);
+    if (!base) return GP_EHIP;
+    // one mesh: the plan fits on the stack, nothing is allocated anywhere
+    gp::MeshDesc d;
+    PlanSizes plan;
+    int rc = plan_core(c->cfg, &m->nt, &m->nv, 1, &d, &plan);
+    if (rc != GP_OK) return rc;
+    if (plan.tmp_bytes > GP_NOALLOC_SCRATCH_BYTES) return GP_ETOOBIG;
+    DeviceGuard g(c->device);
+    gp::RunBuffers rb;
+    uint8_t *tflag = nullptr, *pl = nullptr;
+    int32_t *lpos = nullptr;
+    layout_scratch(plan, &d, 1, base, &rb, &tflag, &pl, &lpos);
+    d.xy = m->xy;
+    d.org = m->org;
+    d.twin = m->twin;
+    d.next_o = out->next;
+    d.prev_o = out->prev;
+    d.seeds = out->seeds;
+    d.loop_off = out->loop_off;
+    d.loop_he = out->loop_he;
+    d.tflag = tflag;
+    d.pl = pl;
+    d.lpos = lpos;
+    d.ctr = rb.ctrs;
+    hipStream_t s = c->stream;
+    // every counter and list the kernels use is cleared by the chain itself
+    // (no memset node, so the call can be captured into a graph)
+    if (gp::launch_put_desc(d, const_cast<gp::MeshDesc *>(rb.descs), s) != hipSuccess ||
+        gp::launch_pipeline(c->cfg, rb, s, nullptr, nullptr) != hipSuccess ||
+        gp::launch_export_counts(rb.ctrs, reinterpret_cast<int32_t *>(counts), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GP_EHIP;
+    }
+    return GP_OK;
 }
 
 int gpolylla_result_info(gp_result *x, gp_result_info *info) {
