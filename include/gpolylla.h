@@ -229,8 +229,8 @@ typedef struct {
  *   counts: caller-allocated device memory; receives the counts of the run
  * The run's scratch (labels, lists, per-tile totals) lives in one static
  * array of GP_NOALLOC_SCRATCH_BYTES per device, set up by gpolylla_ctx_create
- * and held until the process ends; a mesh whose scratch does not fit (about
- * four million triangles with the default launch shapes) is refused with
+ * and held until the process ends; a mesh whose scratch does not fit (above
+ * about 4.9 million triangles with the default launch shapes) is refused with
  * GP_ETOOBIG before anything is queued.  Every call on one device shares
  * that array: calls on one context are ordered by its stream, and calls that
  * overlap on one device (other contexts or streams) race and must not be made.

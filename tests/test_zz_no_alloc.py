@@ -54,11 +54,22 @@ def test_noalloc_matches_mesh_on_two_calls():
 
 
 def test_noalloc_refuses_a_mesh_beyond_the_scratch():
-    m = W.jittered_grid(1536, seed=8, name="g1536")   # 4.7M triangles
+    """A mesh whose scratch needs far more than the static array (8.4M
+    triangles, about 450 MB of scratch against 256 MiB) is refused before any
+    work is queued.  The output buffers are real and large enough anyway, so
+    a refusal that did not happen would fail this test, not the device."""
+    import torch
+    m = W.jittered_grid(2048, seed=8, name="g2048")
+    nt, nh = m.nt, 3 * m.nt
+    dev = torch.device("cuda", 0)
     with gp.Context(0) as ctx:
         h = ctx.build_halfedges(m.xy, m.tri)
-        out = gp.gp_result_dev(1, 1, 1, 1, 1)   # never touched: refused before any work
-        rc = gp.gpolylla_mesh_noalloc(ctx.handle, h.handle, out, 1)
+        bufs = [torch.empty(n, dtype=torch.int32, device=dev) for n in (nh + 1, nh + 1, nt + 1, nt + 2, nh + 1)]
+        counts = torch.zeros(8, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        out = gp.gp_result_dev(*[b.data_ptr() for b in bufs])
+        rc = gp.gpolylla_mesh_noalloc(ctx.handle, h.handle, out, counts.data_ptr())
+        ctx.sync()
         assert rc == gp.GP_ETOOBIG
         # and the context still meshes normally afterwards
         r = ctx.mesh(h)
