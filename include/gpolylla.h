@@ -230,7 +230,7 @@ typedef struct {
  * The run's scratch (labels, lists, per-tile totals) lives in one static
  * array of GP_NOALLOC_SCRATCH_BYTES per device, set up by gpolylla_ctx_create
  * and held until the process ends; a mesh whose scratch does not fit (above
- * about 4.9 million triangles with the default launch shapes) is refused with
+ * about 4.0 million triangles with the default launch shapes) is refused with
  * GP_ETOOBIG before anything is queued.  Every call on one device shares
  * that array: calls on one context are ordered by its stream, and calls that
  * overlap on one device (other contexts or streams) race and must not be made.
@@ -276,7 +276,9 @@ int gpolylla_serve_submit(gp_server *srv, const int32_t *xy, int32_t nv, const i
  * host-resident result (gpolylla_result_info / _copy / _free work on it;
  * gpolylla_result_device does not).  Returns the request's status (its build
  * or meshing error), GP_ETIMEDOUT, or GP_EINVAL for an unknown ticket.  A
- * ticket can be waited for once.  Thread-safe. */
+ * ticket can be waited for once; while one thread waits for it, a wait from
+ * another thread returns GP_EINVAL at once (after GP_ETIMEDOUT it can be
+ * waited for again).  Thread-safe. */
 int gpolylla_serve_wait(gp_server *srv, uint64_t ticket, int32_t timeout_ms, gp_result **out);
 int gpolylla_serve_stats(gp_server *srv, gp_serve_stats *stats);
 /* Clears the latency and throughput statistics (after a warm-up).  Requests

@@ -210,22 +210,32 @@ def gpolylla_ctx_pool_bytes(ctx) -> tuple[int, int]:
     return held.value, used.value
 
 
-def _as_input(a, dtype_cols):
-    """Returns (pointer, count, keepalive, on_device)."""
+def _as_input(a, dtype_cols, device=None):
+    """Returns (pointer, count, keepalive, on_device).  A device tensor must
+    be contiguous int32 of shape (n, dtype_cols) or (n * dtype_cols,), on
+    `device` when that is given."""
     if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
         if a.is_cuda:
             import torch
             if a.dtype != torch.int32 or not a.is_contiguous():
                 raise ValueError("device inputs must be contiguous int32 tensors")
+            if a.numel() % dtype_cols != 0 or (a.dim() >= 2 and (a.dim() > 2 or a.shape[-1] != dtype_cols)):
+                raise ValueError(f"a device input of shape {tuple(a.shape)} is not (n, {dtype_cols})")
+            if device is not None and a.device.index != device:
+                raise ValueError(f"input on cuda:{a.device.index}, context on cuda:{device}")
             return ctypes.c_void_p(a.data_ptr()), a.numel() // dtype_cols, a, True
         a = a.numpy()
-    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1, dtype_cols))
+    arr = np.asarray(a, dtype=np.int32)
+    if arr.size % dtype_cols != 0 or (arr.ndim >= 2 and (arr.ndim > 2 or arr.shape[-1] != dtype_cols)):
+        raise ValueError(f"an input of shape {arr.shape} is not (n, {dtype_cols})")
+    arr = np.ascontiguousarray(arr.reshape(-1, dtype_cols))
     return ctypes.c_void_p(arr.ctypes.data), arr.shape[0], arr, False
 
 
-def gpolylla_build_halfedges(ctx, xy, tri, flags: int = 0):
-    pxy, nv, kxy, dxy = _as_input(xy, 2)
-    ptri, nt, ktri, dtri = _as_input(tri, 3)
+def gpolylla_build_halfedges(ctx, xy, tri, flags: int = 0, device=None):
+    """device: the context's device, to check device tensors against."""
+    pxy, nv, kxy, dxy = _as_input(xy, 2, device)
+    ptri, nt, ktri, dtri = _as_input(tri, 3, device)
     if dxy != dtri:
         raise ValueError("xy and tri must both be host arrays or both device tensors")
     if dxy:
@@ -423,9 +433,10 @@ class Context:
                  block: int = 0, items: int = 0):
         opts = gp_ctx_opts(pool_bytes, int(stream) if stream else None, int(profile), block, items)
         self.handle = gpolylla_ctx_create(device, opts)
+        self.device = device
 
     def build_halfedges(self, xy, tri, flags: int = 0) -> Mesh:
-        return Mesh(self, gpolylla_build_halfedges(self.handle, xy, tri, flags))
+        return Mesh(self, gpolylla_build_halfedges(self.handle, xy, tri, flags, self.device))
 
     def mesh(self, mesh: Mesh, flags: int = 0) -> Result:
         return Result(self, gpolylla_mesh(self.handle, mesh.handle, flags))

@@ -5,21 +5,10 @@
 //   org[3T]     origin vertex of each half-edge (counter-clockwise corners)
 //   twin[3T]    opposite half-edge, -1 on the boundary
 //   tflag[T]    uint8 per triangle: bits 0-1 local index of the longest edge,
-//               bits 2-4 frontier bit of local edges 0..2, bit 5 seed (k_label
-//               writes bits 0-1 and bit 7, "the longest length is shared";
-//               k_relink rewrites the byte without bit 7)
+//               bits 2-4 frontier bit of local edges 0..2, bit 5 seed
 //   pl[T]       uint8 per triangle: 0, or (min(L,63) << 2 | i) when half-edge
 //               3t+i is the minimum of a loop of length L
 //   next_o/prev_o[3T], seeds[<=T], loop_off[<=T+1], loop_he[<=3T] (outputs)
-//
-// Per compaction tile of a run (one tile = block_compact * items_compact
-// triangles of one mesh):
-//   status      (loops << 32 | half-edges) of the loops whose minimum lies in
-//               the tile, then the tile's exclusive prefix within its chunk
-//   bcnt        ints used in the tile's bucket
-//   bucket      bucket_cap ints: loops stored by the kernels that walked
-//               them, each as a header (kRecHeader | local triangle of the
-//               minimum << 16 | length) and its half-edges from the minimum
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,6 +56,7 @@ struct MeshDesc {
     int32_t *seeds;
     int32_t *loop_off;
     int32_t *loop_he;
+    int32_t *lpos;       // per triangle: where k_walk stored the loop whose minimum it holds
     MeshCounters *ctr;
     int32_t nt;
     int32_t nv;
@@ -83,13 +73,11 @@ struct ListEntry {
     int32_t he;
 };
 
-// a loop whose half-edges k_emit writes: minimum mn, first output slot off,
-// length len
+// a loop whose half-edges k_emit writes: minimum mn, first output slot off
 struct EmitEntry {
     int32_t mesh;
     int32_t mn;
     int32_t off;
-    int32_t len;
 };
 
 // Lists appended to by many workgroups are split into kStripes stripes, each
@@ -128,34 +116,28 @@ struct RunBuffers {
     EmitEntry *emit;         // striped: loops k_compact leaves to k_emit
     int32_t *emit_counts;    // kStripes counters, kStripePad ints apart
     int32_t emit_cap;        // per stripe
-    int32_t *bcnt;           // per compaction tile: ints used in its bucket
-    int32_t *bucket;         // per compaction tile: bucket_cap ints of stored loops
-    int32_t bucket_cap;
+    int32_t *wbuf;           // striped: walked loops (rotation index, then half-edges)
+    int32_t *wbuf_counts;    // kStripes counters, kStripePad ints apart
+    int32_t wbuf_cap;        // ints per stripe
 };
 
-// k_walk walks each loop from both ends at once and records each end's
-// half-edges in LDS, up to this many per end; loops longer than
-// 2 * kWalkBuf - 1 are left to k_emit
-constexpr int kWalkBuf = 12;
+// k_walk records each chain's half-edges in LDS, up to this many; longer
+// loops are left to k_emit
+constexpr int kWalkBuf = 16;
+constexpr int kWalkItems = 1;   // chains per k_walk thread
 constexpr int kScanChunk = 1024;   // compaction tiles per k_tile_scan block
-// stored loop records: a header with the top bit set (half-edges are >= 0)
-constexpr uint32_t kRecHeader = 0x80000000u;
-// bucket ints per triangle of a compaction tile
-constexpr int kBucketPerTri = 2;
 // k_compact's LDS holds up to this many loop half-edges per 4 triangles of
 // its tile (2.75 per triangle; meshes average about 2 or fewer).  A tile
-// with more writes its loops straight to global memory.  Beside them: one
-// seed and one offset per triangle, the bucket record of each triangle's
-// loop (int16), and the first kBucketStage ints of the tile's bucket.
+// with more writes its loops straight to global memory.  With one seed and
+// one offset per triangle that is 19 bytes per triangle, so eight tiles of
+// 1024 triangles share a CU's LDS.
 constexpr int kCompactHe4 = 11;
-constexpr int kBucketStage = 256;
 __host__ __device__ inline int compact_he_cap(int tile) { return tile / 4 * kCompactHe4; }
 inline size_t compact_lds_bytes(int tile) {
-    return sizeof(int) * ((size_t)compact_he_cap(tile) + 2 * (size_t)tile + kBucketStage) +
-           sizeof(int16_t) * (size_t)tile;
+    return sizeof(int) * ((size_t)compact_he_cap(tile) + 2 * (size_t)tile);
 }
 
-enum KernelId { K_LABEL = 0, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
+enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.

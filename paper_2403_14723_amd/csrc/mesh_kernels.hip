@@ -4,31 +4,29 @@
 // (a plain call is a batch of one).  Streaming kernels tile each mesh
 // separately, so a workgroup never straddles two meshes and every index it
 // handles is local to one mesh; data-dependent work (barrier tips, repair
-// seeds, fix-ups, loops that leave a tile) goes through small device lists
-// read by persistent grids.
+// seeds, fix-ups) goes through small device lists read by persistent grids.
 //
 // Kernel chain (the eight kernels of the paper's Section 6 / Algorithm 7,
 // regrouped so that every step reads its inputs contiguously):
-//   k_label     longest edge of every triangle (Section 6.1, Algorithm 8);
-//               also clears the run's counters and per-tile totals
+//   k_init      clears run counters, per-mesh counters and scan tile status
+//   k_label     longest edge of every triangle (Section 6.1, Algorithm 8)
 //   k_relink    frontier bits of every half-edge (Section 6.2, Algorithm 9),
 //               the seed bit of terminal edges (Section 6.3, Algorithm 10),
 //               then next/prev of every frontier half-edge by turning around
-//               its target / origin (Section 6.5, Algorithm 12); barrier
-//               tips; every loop that closes inside the tile is walked from
-//               the tile's own next' (Sections 6.5.1-6.6)
+//               its target / origin (Section 6.5, Algorithm 12); barrier tips
 //   k_repair    middle edge at every barrier tip (Section 6.4, Algorithm 11)
 //   k_fixup     next/prev again around both ends of every new frontier edge
-//   k_walk      for every seed whose loop leaves its k_relink tile and every
-//               seed made by the repair: walk the loop from both ends at
-//               once, record its minimum and length at the minimum's
-//               triangle and store it in the bucket of the minimum's
-//               compaction tile (Sections 6.5.1-6.6, Algorithms 13-14)
+//   k_walk      for every seed k_relink left open and every seed made by the
+//               repair: move to a frontier half-edge of its polygon
+//               (Section 6.5.1, Algorithm 13), walk the loop, and record its
+//               minimum and length at the minimum's triangle (Section 6.6,
+//               Algorithm 14).  Polygons of one or two triangles are settled
+//               by k_relink itself.
 //   k_tile_scan exclusive scan of the per-tile loop totals that k_relink and
 //               k_walk accumulate (Section 6.7)
-//   k_compact   writes seeds, loop offsets and the loops of every tile from
-//               its prefix (Section 6.7)
-//   k_emit      writes the loops no kernel stored, from both ends
+//   k_compact   writes seeds, loop offsets and the loops of up to four
+//               half-edges of every tile from its prefix (Section 6.7)
+//   k_emit      writes the longer loops at the offsets k_compact reserved
 //
 // Label byte per triangle (tflag):
 //   bits 0-1  local index of the longest edge
@@ -39,11 +37,10 @@
 
 namespace gp {
 
-const char *const kKernelNames[K_COUNT] = {"k_label", "k_relink", "k_repair",  "k_fixup",
-                                           "k_walk",  "k_tile_scan", "k_compact", "k_emit"};
+const char *const kKernelNames[K_COUNT] = {"k_init", "k_label",     "k_relink",  "k_repair", "k_fixup",
+                                           "k_walk", "k_tile_scan", "k_compact", "k_emit"};
 
 constexpr uint32_t kSeedBit = 1u << 5;
-constexpr uint32_t kTieBit = 1u << 7;   // written by k_label only
 
 // The mesh arrays reached through the descriptor table live in global
 // memory; saying so lets the compiler use global (not flat) loads and stores
@@ -154,18 +151,6 @@ __device__ __forceinline__ int wave_incl_scan(int a) {
     a += dpp_or_zero<0x142, 0xa>(a);
     a += dpp_or_zero<0x143, 0xc>(a);
     return a;
-}
-
-// n consecutive slots per lane from a counter, one atomic per wave (LDS or
-// global memory); returns the lane's first slot.  Every lane of the wave must
-// be active.
-__device__ __forceinline__ int wave_alloc(int *ctr, int n) {
-    const int incl = wave_incl_scan(n);
-    const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-    int base = 0;
-    if (tot > 0 && __lane_id() == kWave - 1) base = atomicAdd(ctr, tot);
-    base = __builtin_amdgcn_readlane(base, kWave - 1);
-    return base + incl - n;
 }
 
 // Exclusive block scan of a pair; lds must hold 66 ints.
@@ -280,106 +265,39 @@ __device__ __forceinline__ void load_to_lds(int *dst, gcint src, int n) {
     for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
 }
 
-// Copies n bytes from LDS src to global dst; both 4-byte aligned; every byte
-// is ANDed with keep.
-__device__ __forceinline__ void store_bytes_from_lds(gu8 dst, const uint8_t *src, int n, uint8_t keep) {
-    const int B = blockDim.x, tid = threadIdx.x;
-    const uint32_t *s4 = reinterpret_cast<const uint32_t *>(src);
-    GLOBAL uint32_t *d4 = reinterpret_cast<GLOBAL uint32_t *>(dst);
-    const uint32_t k4 = 0x01010101u * keep;
-    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k] & k4;
-    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k] & keep;
-}
-
 // ---------------------------------------------------------------------------
-// loop records
+// k_init
 // ---------------------------------------------------------------------------
 
-// Loop byte of the minimum's triangle: (min(len, kPlMax) << 2) | local
-// index of the minimum.  Length code 1 (no loop is that short) marks a loop
-// of four whose second triangle is t + 1; its low bits then hold the local
-// index of that triangle's terminal edge, and the minimum is the lower of
-// the two frontier half-edges of t.
-__device__ __forceinline__ uint8_t loop_code(int mn, int len) {
-    return (uint8_t)(((len < kPlMax ? len : kPlMax) << 2) | (mn - 3 * tri_of(mn)));
-}
-constexpr int kPlQuadNext = 1;
-
-__device__ __forceinline__ int code_len(uint32_t code) {
-    const int l = (int)(code >> 2);
-    return l == kPlQuadNext ? 4 : l;
-}
-
-// Where loops are stored for compaction.
-struct Buckets {
-    uint64_t *agg;    // per compaction tile: (loops << 32 | half-edges)
-    int32_t *bcnt;    // per compaction tile: ints used
-    int32_t *bucket;  // per compaction tile: cap ints
-    int cap;
-    int cmp_tb;       // triangles per compaction tile
-};
-
-// Stores a loop of len half-edges whose minimum mn starts it in the bucket
-// of mn's compaction tile: a header, then get(0..len-1).  A bucket that
-// cannot take the whole record keeps the part it has room for as a record
-// nobody reads (header with local triangle 0x7fff, zeros after it), so that
-// every int below the bucket's end belongs to a complete record.  Returns
-// whether the loop was stored; a loop not stored is written by k_emit.
-template <class GET>
-__device__ __forceinline__ bool bucket_put(const Buckets &bk, const MeshDesc &d, int mn, int len, GET get) {
-    const int tm = tri_of(mn), ct = tm / bk.cmp_tb;
-    const size_t tile = (size_t)d.cmp_tile0 + ct;
-    const int pos = atomicAdd(&bk.bcnt[tile], len + 1);
-    gint rec = (gint)bk.bucket + tile * bk.cap + pos;
-    if (pos + len + 1 <= bk.cap) {
-        rec[0] = (int)(kRecHeader | ((uint32_t)(tm - ct * bk.cmp_tb) << 16) | (uint32_t)len);
-        for (int i = 0; i < len; i++) rec[1 + i] = get(i);
-        return true;
+__global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t *status, int nstatus,
+                       int32_t *walk_counts, int32_t *emit_counts, int32_t *wbuf_counts) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    if (i < kStripes) {
+        walk_counts[i * kStripePad] = 0;
+        emit_counts[i * kStripePad] = 0;
+        wbuf_counts[i * kStripePad] = 0;
     }
-    if (pos < bk.cap) {
-        rec[0] = (int)(kRecHeader | (0x7fffu << 16));
-        for (int i = pos + 1; i < bk.cap; i++) rec[i - pos] = 0;
+    if (i == 0) {
+        rc->ntips = 0;
+        rc->unused = 0;
+        rc->nfix = 0;
+        rc->tile_ctr = 0;
+        rc->err = 0;
     }
-    return false;
-}
-
-// Adds one loop (minimum mn, length len) to the totals of mn's compaction tile.
-__device__ __forceinline__ void agg_add(const Buckets &bk, const MeshDesc &d, int mn, int len) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(bk.agg + d.cmp_tile0 + tri_of(mn) / bk.cmp_tb),
-              (1ull << 32) | (unsigned long long)(uint32_t)len);
+    for (int k = i; k < nmesh; k += stride) {
+        MeshCounters z = {};
+        ctrs[k] = z;
+    }
+    for (int k = i; k < nstatus; k += stride) status[k] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
-// k_label: longest edge of each triangle; clears the run's counters
+// k_label: longest edge of each triangle
 // ---------------------------------------------------------------------------
-
-struct ClearArgs {
-    RunCounters *rc;
-    MeshCounters *ctrs;
-    int nmesh;
-    uint64_t *status;
-    int32_t *bcnt;
-    int ntiles;   // compaction tiles of the run
-    int32_t *walk_counts, *emit_counts;
-};
 
 template <int ITEMS>
-__global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ descs, int nmesh, ClearArgs ca) {
-    // the counters, list sizes and per-tile totals of the run start at zero
-    // for the kernels that follow (nothing in this kernel uses them)
-    {
-        const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-        for (int k = gid; k < ca.ntiles; k += stride) {
-            ca.status[k] = 0ull;
-            ca.bcnt[k] = 0;
-        }
-        for (int k = gid; k < ca.nmesh; k += stride) ca.ctrs[k] = MeshCounters{};
-        if (gid < kStripes) {
-            ca.walk_counts[gid * kStripePad] = 0;
-            ca.emit_counts[gid * kStripePad] = 0;
-        }
-        if (gid == 0) *ca.rc = RunCounters{};
-    }
+__global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ descs, int nmesh) {
     extern __shared__ int4 lds_raw[];
     int *s_org = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x;
@@ -432,7 +350,7 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
                     best = i;
                 }
             }
-            best |= (int)kTieBit;   // counted by k_relink
+            atomicAdd(&d.ctr->nties, 1);
         }
         tflag[t] = (uint8_t)best;
     }
@@ -440,27 +358,67 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
 
 // ---------------------------------------------------------------------------
 // k_relink: frontier and seed bits, next/prev of every frontier half-edge,
-// barrier tips, loops that close inside the tile
+// barrier tips
 //
-// Phase 1 derives each triangle's frontier bits and seed bit from its own
-// longest-edge label and its neighbours' (Section 6.2-6.3) and keeps the
-// tile's label bytes and twins in LDS.  Phase 2 links every frontier
-// half-edge to the next frontier half-edge around its target (next') and its
-// origin (prev') (Section 6.5): the edge after it in its own triangle when
-// that edge is frontier, else a turn that starts in the neighbour across it.
-// The first candidate of a turn is decided by one LDS read when the
-// neighbour lies in the tile; turns that go on, and candidates outside the
-// tile, go to an LDS queue that the first lanes of the block run.  A
-// candidate outside the tile derives its frontier bit from the longest-edge
-// labels, which no kernel changes during this pass (the tile's label bytes
-// are written back with their longest-edge bits unchanged).  Polygons of one
-// or two triangles are settled from labels already in registers; the loops
-// of other seeds are walked through the tile's next' in LDS, and those that
-// leave the tile (or pass a barrier tip, which the repair will change) go to
-// the walk list.
+// One thread per triangle.  Phase 1 derives each triangle's frontier bits
+// and seed bit from its own longest-edge label and its neighbours' (Section
+// 6.2-6.3) and keeps the byte in LDS.  Phase 2 turns around the ends of every
+// frontier half-edge (Section 6.5): a candidate in the tile reads its
+// frontier bit from LDS; one outside derives it from the longest-edge labels,
+// which no kernel changes during this pass (the tile's label bytes are
+// written back with their longest-edge bits unchanged).  Each thread loads
+// its triangles' twins and stores their next'/prev' itself (12 contiguous
+// bytes per triangle); the label and loop bytes go out through LDS in whole
+// words.
 // ---------------------------------------------------------------------------
 
-// Frontier test of half-edge c during k_relink.
+// Loop byte of the minimum's triangle: (min(len, kPlMax) << 2) | local
+// index of the minimum.  Length code 1 (no loop is that short) marks a loop
+// of four whose second triangle is t + 1; its low bits then hold the local
+// index of that triangle's terminal edge, and the minimum is the lower of
+// the two frontier half-edges of t.
+__device__ __forceinline__ uint8_t loop_code(int mn, int len) {
+    return (uint8_t)(((len < kPlMax ? len : kPlMax) << 2) | (mn % 3));
+}
+constexpr int kPlQuadNext = 1;
+
+// Records a walked loop (minimum mn, length len) once: the walker that sets
+// the byte of the minimum's triangle adds the loop to the totals of that
+// triangle's compaction tile.  After a repair several seeds of one polygon
+// walk the same loop; only the first counts it.  claim_issue ORs the code in
+// and returns the word as it was (every walker of the loop writes the same
+// code, so OR-ing is safe); claim_won reads the verdict from it, so other
+// memory operations can be issued while the atomic is in flight.
+__device__ __forceinline__ uint32_t claim_issue(const MeshDesc &d, int mn, int len) {
+    const int tm = tri_of(mn);
+    uint32_t *w = reinterpret_cast<uint32_t *>(d.pl) + (tm >> 2);
+    return atomicOr(w, (uint32_t)loop_code(mn, len) << (8 * (tm & 3)));
+}
+__device__ __forceinline__ bool claim_won(const MeshDesc &d, uint32_t old, int mn, int len, uint64_t *agg,
+                                          int cmp_tb) {
+    const int tm = tri_of(mn);
+    if ((old >> (8 * (tm & 3))) & 0xffu) return false;
+    atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + tm / cmp_tb),
+              (1ull << 32) | (unsigned long long)(uint32_t)len);
+    return true;
+}
+
+// Label bit 6 of a loop's minimum triangle: k_walk stored the loop in the
+// scratch pool (at lpos of that triangle); k_relink writes the label bytes
+// with the bit clear.
+constexpr uint32_t kStoredBit = 1u << 6;
+
+// Copies n bytes from LDS src to global dst; both 4-byte aligned.
+__device__ __forceinline__ void store_bytes_from_lds(gu8 dst, const uint8_t *src, int n) {
+    const int B = blockDim.x, tid = threadIdx.x;
+    const uint32_t *s4 = reinterpret_cast<const uint32_t *>(src);
+    GLOBAL uint32_t *d4 = reinterpret_cast<GLOBAL uint32_t *>(dst);
+    for (int k = tid; k < n / 4; k += B) d4[k] = s4[k];
+    for (int k = (n & ~3) + tid; k < n; k += B) dst[k] = src[k];
+}
+
+// Frontier test of half-edge c during k_relink.  Lc is the longest-edge label
+// of c's triangle, or -1 when it has not been loaded.
 struct TileLabels {
     gcint twin;
     gcu8 tflag;                          // longest-edge bits (0-1) only are read
@@ -505,6 +463,12 @@ __device__ __forceinline__ int run_turn(const TileLabels &T, int c, int Lc, bool
     return -1;
 }
 
+// Records a barrier tip found in a k_relink tile in the tile's LDS list
+// (appended to the global list once per block); straight to the global list
+// when the LDS list is full.
+__device__ __forceinline__ void tile_tip(int *s_tip, int *s_ntip, int tcap, int local_he, int base, RunCounters *rc,
+                                         ListEntry *tips, int cap_tips, const MeshDesc &d, int mi, bool &err);
+
 // Appends barrier tip he of mesh mi to the tip list.
 __device__ __forceinline__ void push_tip(RunCounters *rc, ListEntry *tips, int cap_tips, const MeshDesc &d, int mi,
                                          int he, bool &err) {
@@ -518,408 +482,357 @@ __device__ __forceinline__ void push_tip(RunCounters *rc, ListEntry *tips, int c
     }
 }
 
-struct RelinkArgs {
-    const MeshDesc *descs;
-    int nmesh;
-    RunCounters *rc;
-    ListEntry *tips;
-    int cap_tips;
-    ListEntry *walk;
-    int32_t *walk_counts;
-    int walk_cap;
-    Buckets bk;
-};
+__device__ __forceinline__ void tile_tip(int *s_tip, int *s_ntip, int tcap, int local_he, int base, RunCounters *rc,
+                                         ListEntry *tips, int cap_tips, const MeshDesc &d, int mi, bool &err) {
+    const int i = atomicAdd(s_ntip, 1);
+    if (i < tcap)
+        s_tip[i] = local_he;
+    else
+        push_tip(rc, tips, cap_tips, d, mi, 3 * base + local_he, err);
+}
 
-// The per-block counters of k_relink in LDS.
-struct RelinkShared {
-    int nq;      // turns queued
-    int ntip;    // tips found
-    int nopen;   // seeds whose loop is walked in the tile
-    int nties;
-    int nwalk;   // walk-list entries of the block (reserved per wave)
-    int settled_c, settled_l;   // loops settled here (block in one compaction tile)
-};
+// Frontier bit of half-edge c of a triangle outside the tile whose
+// longest-edge label is Lc.
+__device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc) {
+    const int tc = c / 3, lc = c - 3 * tc;
+    if (Lc == lc) return false;
+    const int g = T.twin[c];
+    if (g < 0) return true;
+    const int tg = g / 3;
+    return (int)(T.tflag[tg] & 3u) != g - 3 * tg;
+}
 
 template <int ITEMS>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_relink(RelinkArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
+                                                  RunCounters *rc, ListEntry *tips, int cap_tips,
+                                                  ListEntry *walk, int32_t *walk_counts, int walk_cap,
+                                                  uint64_t *agg, int cmp_tb) {
     extern __shared__ int4 lds_raw[];
+    int *lds = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x, TB = B * ITEMS;
-    int *s_tw = reinterpret_cast<int *>(lds_raw);                // the tile's twins
-    int *s_nx = s_tw + 3 * TB;                                    // the tile's next'
-    uint8_t *s_f = reinterpret_cast<uint8_t *>(s_nx + 3 * TB);   // label bytes
-    uint8_t *s_pl = s_f + TB;                                     // loop bytes
-    int *s_q = reinterpret_cast<int *>(s_pl + TB);                // queued turns, 2 ints each
+    int *s_tw = lds;                                            // the tile's twins
+    uint8_t *s_f = reinterpret_cast<uint8_t *>(lds + 3 * TB);   // label bytes
+    uint8_t *s_pl = s_f + TB;                                   // loop bytes
+    int *s_q = reinterpret_cast<int *>(s_pl + TB);              // queued turns, 2 ints each
     const int qcap = TB / 2;
-    int *s_tip = s_q + 2 * qcap;                                  // barrier tips found here
+    int *s_tip = s_q + 2 * qcap;                                // barrier tips found here
     const int tcap = TB / 4;
-    __shared__ RelinkShared sh;
+    __shared__ int s_ntip;
     // loops settled here, per compaction tile, when the tile's triangles
     // span several of them (a relink tile of <= 1024 triangles, compaction
     // tiles of >= 64: at most 17)
     constexpr int kSpan = 1024 / 64 + 1;
     __shared__ int s_aggc[kSpan], s_aggl[kSpan];
-    if (tid == 0) sh = RelinkShared{};
-    if (tid < kSpan) {
-        s_aggc[tid] = 0;
-        s_aggl[tid] = 0;
+    if (threadIdx.x == 0) s_ntip = 0;
+    if (threadIdx.x < kSpan) {
+        s_aggc[threadIdx.x] = 0;
+        s_aggl[threadIdx.x] = 0;
     }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int mi = find_mesh<1>(a.descs, a.nmesh, tile);
-    const MeshDesc &d = a.descs[mi];
+    const int mi = find_mesh<1>(descs, nmesh, tile);
+    const MeshDesc &d = descs[mi];
     const int nt = d.nt;
     const gcint twin = (gcint)(d.twin);
     const gu8 tflag = (gu8)(d.tflag);
+    const gint nxo = (gint)(d.next_o), pvo = (gint)(d.prev_o);
     const int base = (tile - d.he_tile0) * TB;
     const int cnt = min(TB, nt - base);
     if (cnt <= 0) return;   // an empty mesh's tile (the whole block)
-    const int hb = 3 * base;
-    const int cmp_tb = a.bk.cmp_tb;
-    // the block's triangles lie in one compaction tile unless that tile is
-    // smaller than this one or not aligned with it
-    const int ct0 = base / cmp_tb;
-    const bool one = ct0 == (base + cnt - 1) / cmp_tb;
-
-    // ---- phase 1: labels of the triangle and its neighbours -> frontier, seed
-    // Every load is issued unconditionally (indices clamped to 0, results
-    // masked after) so that all of them are in flight together.
-    // per item: twins (g) and their triangles (q) as 3-vectors, so that an
-    // element picked by a label is a register select, not an array in memory
-    v3i g[ITEMS], q[ITEMS];
-    int ties = 0;
-    uint32_t f[ITEMS];    // label byte: L | frontier bits << 2 | seed bit
-    uint32_t pk[ITEMS];   // bits 2i: local index of twin(3t+i); bits 6+2i: longest edge of its triangle
-    {
-        uint32_t own[ITEMS], fn[ITEMS][3];
+    // phase 1: labels of the triangle and its neighbours -> frontier, seed.
+    // Each thread loads its triangles' twins itself (12 contiguous bytes per
+    // triangle, so a wave's loads are contiguous) and issues the label
+    // gathers as soon as they arrive; the twins go to LDS for the turns of
+    // phase 2, published by the barrier after the label bytes.  Every load is
+    // issued unconditionally (indices clamped to 0, results masked after) so
+    // that all of them are in flight together.
+    int tw[ITEMS][3];
+    uint32_t f[ITEMS], fn[ITEMS][3];
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            const int lt = j * B + tid;
-            const bool ok = lt < cnt;
-            const v3i_a4 gv = *(GLOBAL const v3i_a4 *)(twin + 3 * (size_t)(base + (ok ? lt : 0)));
-            g[j] = ok ? v3i{gv.x, gv.y, gv.z} : v3i{-1, -1, -1};
-            own[j] = tflag[base + (ok ? lt : 0)];
-        }
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        const bool ok = lt < cnt;
+        const v3i_a4 g = *(GLOBAL const v3i_a4 *)(twin + 3 * (size_t)(base + (ok ? lt : 0)));
+        tw[j][0] = ok ? g.x : -1;
+        tw[j][1] = ok ? g.y : -1;
+        tw[j][2] = ok ? g.z : -1;
+        f[j] = tflag[base + (ok ? lt : 0)];
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++)
+        for (int i = 0; i < 3; i++) fn[j][i] = tflag[tri_of(tw[j][i] < 0 ? 0 : tw[j][i])];
+    }
 #pragma unroll
-            for (int i = 0; i < 3; i++) {
-                q[j][i] = tri_of(g[j][i] < 0 ? 0 : g[j][i]);
-                fn[j][i] = tflag[q[j][i]];
-            }
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt < cnt) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            const int lt = j * B + tid;
-            const int t = base + lt;
-            const uint32_t L = own[j] & 3u;
-            ties += (lt < cnt && (own[j] & kTieBit)) ? 1 : 0;
-            uint32_t out = L, p = 0;
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                const int gi = g[j][i];
-                const int ri = gi - 3 * q[j][i];
-                const uint32_t Ln = fn[j][i] & 3u;
-                const bool tl = gi >= 0 && (int)Ln == ri;   // twin is its triangle's longest edge
-                // frontier: boundary, or the longest edge of neither triangle
-                out |= (gi < 0 || ((int)L != i && !tl)) ? 1u << (2 + i) : 0u;
-                // terminal edge: longest on both sides (the lower half-edge
-                // holds the seed), or longest and on the boundary
-                out |= ((int)L == i && (gi < 0 || (tl && 3 * t + i < gi))) ? kSeedBit : 0u;
-                p |= ((uint32_t)(gi < 0 ? 0 : ri) << (2 * i)) | (Ln << (6 + 2 * i));
-            }
-            f[j] = lt < cnt ? out : 0u;
-            pk[j] = p;
-            if (lt < cnt) {
-                s_f[lt] = (uint8_t)out;
-#pragma unroll
-                for (int i = 0; i < 3; i++) s_tw[3 * lt + i] = g[j][i];
-            }
+            for (int i = 0; i < 3; i++) s_tw[3 * lt + i] = tw[j][i];
         }
     }
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        const int t = base + lt;
+        const uint32_t L = f[j] & 3u;
+        uint32_t out = L;
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int g = tw[j][i];
+            fn[j][i] = g >= 0 ? fn[j][i] & 3u : 0u;
+            const bool twin_long = g >= 0 && (int)fn[j][i] == g - 3 * tri_of(g);
+            // frontier: boundary, or the longest edge of neither triangle
+            out |= (g < 0 || ((int)L != i && !twin_long)) ? 1u << (2 + i) : 0u;
+            // terminal edge: longest on both sides (the lower half-edge holds
+            // the seed), or longest and on the boundary
+            out |= ((int)L == i && (g < 0 || (twin_long && 3 * t + i < g))) ? kSeedBit : 0u;
+        }
+        f[j] = lt < cnt ? out : 0u;
+        if (lt < cnt) s_f[lt] = (uint8_t)out;
+    }
     __syncthreads();
-    if (ties) atomicAdd(&sh.nties, ties);
-
-    // ---- phase 2: first candidates, settled polygons, queued turns
-    // next'/prev' of every triangle leave at once as one 12-byte store each
-    // (every line written once and whole); the few turns that go on are
-    // queued and their lanes patch the result in afterwards.  next' also goes
-    // to LDS for the walks through the tile.
-    const TileLabels T = {twin, (gcu8)tflag, s_tw, s_f, base, cnt};
-    const gint nxo = (gint)(d.next_o), pvo = (gint)(d.prev_o);
+    // phase 2: next'/prev' of every frontier half-edge.  The next (previous)
+    // edge in the triangle is taken when it is frontier itself; otherwise the
+    // turn continues in the neighbour across it.  A triangle has at most one
+    // frontier half-edge followed by a non-frontier one and at most one
+    // preceded by one, so each item has at most two turns; nearly all of
+    // them end at their first candidate.  The common path is straight-line
+    // code; only turns that go on, and candidates outside the tile, branch.
+    const TileLabels T = {twin, tflag, s_tw, s_f, base, cnt};
     bool err = false;
-    uint32_t pend[ITEMS];   // turns beyond the LDS queue: bit i next' of 3t+i, bit 3+i prev'
-    int openmask = 0;       // bit j: item j holds a seed whose loop is not settled
-    int scnt = 0, slen = 0; // loops settled here
+    int openmask = 0;   // bit j: item j holds a seed whose loop k_walk must walk
+    int scnt = 0, slen = 0;   // loops settled here: count, half-edges
+    uint8_t codes[ITEMS];
+    uint32_t pend = 0;  // bit 2j (2j+1): the next' (prev') turn of item j goes on
+    int cur[2 * ITEMS], lab[2 * ITEMS], src[2 * ITEMS];   // turn state; src: the
+                                                          // local index of the half-edge
+    int nv3[ITEMS][3], pv3[ITEMS][3];                     // this lane's next'/prev'
+    int qslot[2 * ITEMS];                                 // LDS queue slot of turn k, or -1
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;   // lt >= cnt: f[j] == 0, so nothing is queued
+        const int h0 = 3 * (base + lt);
+        const uint32_t F3 = (f[j] >> 2) & 7u;
+        const uint32_t rn = ((F3 >> 1) | (F3 << 2)) & 7u;   // bit i: edge i+1 frontier
+        const uint32_t rp = ((F3 << 1) | (F3 >> 2)) & 7u;   // bit i: edge i-1 frontier
+        const uint32_t mn = F3 & ~rn, mp = F3 & ~rp;        // at most one bit each
+        // in-triangle values (the turn's slot gets its value when the turn ends)
+        int nxv[3], pvv[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            nxv[i] = ((F3 & rn) >> i) & 1u ? h0 + (i == 2 ? 0 : i + 1) : -1;
+            pvv[i] = ((F3 & rp) >> i) & 1u ? h0 + (i == 0 ? 2 : i - 1) : -1;
+        }
+        // next' turn: from the frontier half-edge na, across x = next(na)
+        const int na = mn ? __builtin_ctz(mn) : 0, x = na == 2 ? 0 : na + 1;
+        const int ux = x == 0 ? tw[j][0] : (x == 1 ? tw[j][1] : tw[j][2]);
+        src[2 * j] = 3 * lt + na;
+        cur[2 * j] = he_next(ux < 0 ? 0 : ux);
+        lab[2 * j] = (int)(x == 0 ? fn[j][0] : (x == 1 ? fn[j][1] : fn[j][2]));
+        // prev' turn: from the frontier half-edge pa, across y = prev(pa)
+        const int pa = mp ? __builtin_ctz(mp) : 0, y = pa == 0 ? 2 : pa - 1;
+        const int uy = y == 0 ? tw[j][0] : (y == 1 ? tw[j][1] : tw[j][2]);
+        src[2 * j + 1] = 3 * lt + pa;
+        cur[2 * j + 1] = he_prev(uy < 0 ? 0 : uy);
+        lab[2 * j + 1] = (int)(y == 0 ? fn[j][0] : (y == 1 ? fn[j][1] : fn[j][2]));
+        // a non-frontier edge is interior: ux, uy >= 0 whenever the turn exists
+        err |= (mn && ux < 0) || (mp && uy < 0);
+        // first candidates: most are frontier half-edges of a triangle in the
+        // tile, which ends the turn at once
+        const int cn = cur[2 * j], tn = tri_of(cn), kn = tn - base;
+        const int cp = cur[2 * j + 1], tq = tri_of(cp), kq = tq - base;
+        const bool inn = (unsigned)kn < (unsigned)cnt, inq = (unsigned)kq < (unsigned)cnt;
+        const uint32_t fbn = s_f[inn ? kn : 0], fbq = s_f[inq ? kq : 0];
+        const bool hitn = mn && inn && fbit(fbn, cn - 3 * tn);
+        const bool hitq = mp && inq && fbit(fbq, cp - 3 * tq);
+        if (hitn) {
+            // next'(h) == twin(h): the target of h is a barrier tip
+            if (cn == (na == 0 ? tw[j][0] : (na == 1 ? tw[j][1] : tw[j][2])))
+                tile_tip(s_tip, &s_ntip, tcap, 3 * lt + na, base, rc, tips, cap_tips, d, mi, err);
+        }
+        const bool pn = mn && !hitn, pp = mp && !hitq;   // turns that go on
+        pend |= (pn ? 1u : 0u) << (2 * j) | (pp ? 1u : 0u) << (2 * j + 1);
+        // this triangle's next'/prev' stay in registers until the tile is done
+        // (a turn that goes on fills its slot later), then go out as one
+        // 12-byte store each, so every line is written once and whole
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            nv3[j][i] = (mn && i == na) ? cn : nxv[i];
+            pv3[j][i] = (mp && i == pa) ? cp : pvv[i];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
         const int t = base + lt, h0 = 3 * t;
-        const uint32_t F3 = (f[j] >> 2) & 7u;   // 0 past the tile: nothing below happens
-        int cN[3], cP[3];
-        uint32_t hN = 0, hP = 0;   // bit x: the first candidate across edge x is frontier
-#pragma unroll
-        for (int x = 0; x < 3; x++) {
-            // the turns across edge x: next' of the frontier half-edge before
-            // x continues at next(twin(x)), prev' of the one after x at
-            // prev(twin(x)); both candidates lie in the neighbour triangle
-            const int gx = g[j][x];
-            const int rx = (int)((pk[j] >> (2 * x)) & 3u);
-            const int rn = rx == 2 ? 0 : rx + 1, rp = rx == 0 ? 2 : rx - 1;
-            cN[x] = gx - rx + rn;
-            cP[x] = gx - rx + rp;
-            const int k = q[j][x] - base;
-            const bool in = gx >= 0 && (unsigned)k < (unsigned)cnt;
-            const uint32_t fx = s_f[in ? k : 0];
-            hN |= (in && ((fx >> (2 + rn)) & 1u)) ? 1u << x : 0u;
-            hP |= (in && ((fx >> (2 + rp)) & 1u)) ? 1u << x : 0u;
-        }
-        int nv[3], pv[3];
-        uint32_t pm = 0, tm = 0;
-#pragma unroll
-        for (int i = 0; i < 3; i++) {
-            const int ia = i == 2 ? 0 : i + 1, ib = i == 0 ? 2 : i - 1;
-            const bool Fi = (F3 >> i) & 1u, Fa = (F3 >> ia) & 1u, Fb = (F3 >> ib) & 1u;
-            const bool hNa = (hN >> ia) & 1u, hPb = (hP >> ib) & 1u;
-            nv[i] = !Fi ? -1 : (Fa ? h0 + ia : cN[ia]);
-            pv[i] = !Fi ? -1 : (Fb ? h0 + ib : cP[ib]);
-            pm |= (Fi && !Fa && !hNa) ? 1u << i : 0u;
-            pm |= (Fi && !Fb && !hPb) ? 8u << i : 0u;
-            // next'(h) == twin(h): the target of h is a barrier tip
-            tm |= (Fi && !Fa && hNa && cN[ia] == g[j][i]) ? 1u << i : 0u;
-        }
-        if (lt < cnt) {
-            *reinterpret_cast<GLOBAL v3i *>(nxo + h0) = v3i{nv[0], nv[1], nv[2]};
-            *reinterpret_cast<GLOBAL v3i *>(pvo + h0) = v3i{pv[0], pv[1], pv[2]};
-            // a tip half-edge's next' is kept complemented (negative) in LDS,
-            // so a walk through the tile that meets it stops
-#pragma unroll
-            for (int i = 0; i < 3; i++) s_nx[3 * lt + i] = ((tm >> i) & 1u) ? ~nv[i] : nv[i];
-        }
-        // tips of this item into the tile's LDS list (rare)
-        if (tm) {
-#pragma unroll
-            for (int i = 0; i < 3; i++) {
-                if (!((tm >> i) & 1u)) continue;
-                const int s = atomicAdd(&sh.ntip, 1);
-                if (s < tcap)
-                    s_tip[s] = 3 * lt + i;
-                else
-                    push_tip(a.rc, a.tips, a.cap_tips, d, mi, h0 + i, err);
-            }
-        }
         // A seed whose polygon is one triangle (boundary terminal edge, both
         // other edges frontier) or two (interior terminal edge, the four
         // other edges frontier) is settled here: its loop is those 3 or 4
         // half-edges.  Such polygons have no interior vertex, so no barrier
         // tip and no repair touches them.  The seed is the lower half-edge of
-        // its terminal edge, so the loop's minimum lies in this triangle.
-        const int L = (int)(f[j] & 3u), la = L == 2 ? 0 : L + 1, lb = L == 0 ? 2 : L - 1;
-        const bool seed = (f[j] & kSeedBit) != 0;
-        const bool cand = seed && ((F3 >> la) & 1u) && ((F3 >> lb) & 1u);
-        const int gL = g[j][L], qL = q[j][L];
-        const bool quad = ((hN & hP) >> L) & 1u;
-        const int rL = (int)((pk[j] >> (2 * L)) & 3u);
-        const uint32_t code = !cand ? 0u
-                              : gL < 0 ? (uint32_t)loop_code(h0, 3)
-                              : !quad ? 0u
-                              : qL == t + 1 ? (uint32_t)((kPlQuadNext << 2) | rL)
-                                            : (uint32_t)loop_code(h0 + (la < lb ? la : lb), 4);
-        openmask |= (seed && !code) ? 1 << j : 0;
-        if (lt < cnt) s_pl[lt] = (uint8_t)code;
-        if (code) {
-            if (one) {
-                scnt += 1;
-                slen += code_len(code);
-            } else {
-                const int k = t / cmp_tb - ct0;
-                atomicAdd(&s_aggc[k], 1);
-                atomicAdd(&s_aggl[k], code_len(code));
-            }
-        }
-        // queue this item's open turns (one LDS atomic per wave)
-        const int slot = wave_alloc(&sh.nq, __popc(pm));
-        uint32_t over = 0;
-        int sl = slot;
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            if (!((pm >> k) & 1u)) continue;
-            if (sl < qcap) {
-                const int i = k % 3;
-                const int x = k < 3 ? (i == 2 ? 0 : i + 1) : (i == 0 ? 2 : i - 1);
-                s_q[2 * sl] = k < 3 ? cN[x] : cP[x];
-                s_q[2 * sl + 1] = ((3 * lt + i) << 3) | (k < 3 ? 4 : 0) | ((int)((pk[j] >> (6 + 2 * x)) & 3u) + 1);
-            } else {
-                over |= 1u << k;
-            }
-            ++sl;
-        }
-        pend[j] = over;
+        // its terminal edge, so the loop's minimum lies in this triangle and
+        // its byte is written here with the rest of the tile.
+        const int L = (int)(f[j] & 3u), a = L == 2 ? 0 : L + 1, b = L == 0 ? 2 : L - 1;
+        const bool cand = (f[j] & kSeedBit) && fbit(f[j], a) && fbit(f[j], b);
+        const int g = L == 0 ? tw[j][0] : (L == 1 ? tw[j][1] : tw[j][2]);
+        const int tp = tri_of(g < 0 ? 0 : g), Lp = g - 3 * tp;
+        const int ap = Lp == 2 ? 0 : Lp + 1, bp = Lp == 0 ? 2 : Lp - 1;
+        const int kp = tp - base;
+        const bool inp = (unsigned)kp < (unsigned)cnt;
+        const uint32_t fp = s_f[inp ? kp : 0];
+        bool quad = fbit(fp, ap) && fbit(fp, bp);
+        if (cand && g >= 0 && !inp)   // partner outside the tile (rare on ordered meshes)
+            quad = outside_fbit(T, 3 * tp + ap, Lp) && outside_fbit(T, 3 * tp + bp, Lp);
+        const uint8_t code = !cand ? (uint8_t)0
+                             : g < 0 ? loop_code(h0, 3)
+                             : !quad ? (uint8_t)0
+                             : tp == t + 1 ? (uint8_t)((kPlQuadNext << 2) | Lp)
+                                           : loop_code(h0 + min(a, b), 4);
+        openmask |= ((f[j] & kSeedBit) && !code) ? 1 << j : 0;
+        s_pl[lt] = code;   // entries past cnt are never stored
+        codes[j] = code;
+        scnt += code ? 1 : 0;
+        slen += !code ? 0 : (code >> 2) == kPlQuadNext ? 4 : (code >> 2);
     }
+    // One block scan places the turns still open in the LDS queue and the
+    // open seeds in the walk list (stripe by tile, one atomic per block), and
+    // totals the loops settled here for their compaction tile.  Each count
+    // fits in 16 bits (at most 2 per triangle, lengths at most 4 per
+    // triangle, tiles of at most 1024 triangles), so two ride in one int.
     {
-        // seeds walked in the tile, and the settled totals: one LDS atomic per wave
-        int o = __popc(openmask), c2 = scnt, l2 = slen;
-        wave_incl_scan2(c2, l2);
-        const int ot = __builtin_amdgcn_readlane(wave_incl_scan(o), kWave - 1);
-        if (__lane_id() == kWave - 1) {
-            if (ot) atomicAdd(&sh.nopen, ot);
-            if (c2) {
-                atomicAdd(&sh.settled_c, c2);
-                atomicAdd(&sh.settled_l, l2);
-            }
+        __shared__ int s_scan[72];
+        __shared__ int s_wbase;
+        int ea, eb, ta, tb;
+        block_excl_scan2((__popc(pend) << 16) | __popc(openmask), (scnt << 16) | slen, ea, eb, ta, tb, s_scan);
+        int eq = ea >> 16;
+        const int eo = ea & 0xffff, tq = ta >> 16, to = ta & 0xffff;
+        const int stripe = tile % kStripes;
+        // the block's triangles lie in one compaction tile unless that tile is
+        // smaller than this one or not aligned with it
+        const bool one = base / cmp_tb == (base + cnt - 1) / cmp_tb;
+        if (tid == 0) {
+            s_wbase = to > 0 ? atomicAdd(&walk_counts[stripe * kStripePad], to) : 0;
+            if (one && tb != 0)
+                atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + base / cmp_tb),
+                          ((unsigned long long)(uint32_t)(tb >> 16) << 32) | (unsigned long long)(tb & 0xffff));
         }
-    }
-    __syncthreads();
-
-    // ---- turns that go on: the queue's, spread over the block's lanes, then
-    // (when the queue was full) each lane's own.  The lane that ends a turn
-    // writes its result over the provisional value.
-    auto finish_turn = [&](int src, bool nxt, int res) {
-        err |= res < 0;
-        if (nxt) {
-            const bool tip = res >= 0 && res == s_tw[src];
-            nxo[hb + src] = res;
-            s_nx[src] = tip ? ~res : res;
-            if (tip) {
-                const int s = atomicAdd(&sh.ntip, 1);
-                if (s < tcap)
-                    s_tip[s] = src;
-                else
-                    push_tip(a.rc, a.tips, a.cap_tips, d, mi, hb + src, err);
-            }
-        } else {
-            pvo[hb + src] = res;
-        }
-    };
-    const int nq_all = sh.nq;
-    const int nq = min(nq_all, qcap);
-    for (int qq = tid; qq < nq; qq += B) {
-        const int w = s_q[2 * qq + 1];
-        finish_turn(w >> 3, (w & 4) != 0, run_turn(T, s_q[2 * qq], (w & 3) - 1, (w & 4) != 0));
-    }
-    if (nq_all > qcap) {   // the queue overflowed (meshes whose polygons are mostly large)
-        // one loop over this lane's left-over turns, its inputs re-read from
-        // LDS and the label bytes (one copy of the turn code)
-        uint64_t left = 0;
+        const int ct0 = base / cmp_tb;   // first compaction tile of this tile
+        if (!one) {   // totals per compaction tile in LDS, one global atomic each below
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) left |= (uint64_t)pend[j] << (6 * j);
-        while (left) {
-            const int bit = __builtin_ctzll(left);
-            left &= left - 1;
-            const int j = bit / 6, k = bit - 6 * j, i = k % 3;
-            const int lt = j * B + tid;
-            const int x = k < 3 ? (i == 2 ? 0 : i + 1) : (i == 0 ? 2 : i - 1);
-            const int gx = s_tw[3 * lt + x];   // interior: the turn crosses edge x
-            if (gx < 0) {
-                err = true;
-                continue;
-            }
-            const int cur = k < 3 ? he_next(gx) : he_prev(gx);
-            finish_turn(3 * lt + i, k < 3, run_turn(T, cur, (int)(tflag[tri_of(gx)] & 3u), k < 3));
-        }
-    }
-    const int nopen = sh.nopen;
-    if (nopen > 0) {
-        if (nq_all > 0) __syncthreads();   // the patched next' in LDS
-        // every seed not settled above: walk its loop through the tile
-        int wlist[ITEMS];
-        int npush = 0, pushm = 0;
-#pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            wlist[j] = 0;
-            if (!((openmask >> j) & 1)) continue;
-            const int lt = j * B + tid;
-            const int t = base + lt, h0 = 3 * t;
-            const uint32_t F3 = (f[j] >> 2) & 7u;
-            const int L = (int)(f[j] & 3u), la = L == 2 ? 0 : L + 1, lb = L == 0 ? 2 : L - 1;
-            // a frontier half-edge of the seed's triangle lies on the loop;
-            // a triangle with none starts with a search (k_walk)
-            const int start = ((F3 >> la) & 1u) ? h0 + la : (((F3 >> lb) & 1u) ? h0 + lb : -1);
-            if (start < 0) {
-                wlist[j] = ~(h0 + L);
-                pushm |= 1 << j;
-                ++npush;
-                continue;
-            }
-            int cur = start, mn = start, len = 0;
-            bool closed = false;
-            while (true) {
-                const int idx = cur - hb;
-                if ((unsigned)idx >= (unsigned)(3 * cnt)) break;   // leaves the tile
-                const int nx = s_nx[idx];
-                if (nx < 0) break;   // a barrier tip (or a corrupt link)
-                ++len;
-                mn = cur < mn ? cur : mn;
-                cur = nx;
-                if (cur == start) {
-                    closed = true;
-                    break;
-                }
-                if (len > 3 * cnt) break;
-            }
-            if (!closed) {
-                wlist[j] = start;
-                pushm |= 1 << j;
-                ++npush;
-                continue;
-            }
-            // the loop is settled: its byte at the minimum's triangle (in
-            // this tile), its record in the bucket, its count in the totals
-            s_pl[tri_of(mn) - base] = loop_code(mn, len);
-            int w = mn;
-            bucket_put(a.bk, d, mn, len, [&](int) {
-                const int v = w;
-                w = s_nx[w - hb];
-                return v;
-            });
-            if (one) {
-                atomicAdd(&sh.settled_c, 1);
-                atomicAdd(&sh.settled_l, len);
-            } else {
-                const int k = tri_of(mn) / cmp_tb - ct0;
+            for (int j = 0; j < ITEMS; j++) {
+                if (!codes[j]) continue;
+                const int k = (base + j * B + tid) / cmp_tb - ct0;
+                const int len = (codes[j] >> 2) == kPlQuadNext ? 4 : (codes[j] >> 2);
                 atomicAdd(&s_aggc[k], 1);
                 atomicAdd(&s_aggl[k], len);
             }
         }
-        // loops that leave the tile: to the walk list (one atomic per wave)
-        const int stripe = tile % kStripes;
-        int e = wave_alloc(&a.walk_counts[stripe * kStripePad], npush);
+#pragma unroll
+        for (int k = 0; k < 2 * ITEMS; k++) {
+            qslot[k] = -1;
+            if (!((pend >> k) & 1u)) continue;
+            if (eq < qcap) {
+                s_q[2 * eq] = cur[k];
+                s_q[2 * eq + 1] = (src[k] << 3) | ((k & 1) == 0 ? 4 : 0) | (lab[k] + 1);
+                qslot[k] = eq;
+                pend &= ~(1u << k);
+            }
+            ++eq;
+        }
+        __syncthreads();
+        if (!one && tid <= (base + cnt - 1) / cmp_tb - ct0 && s_aggc[tid] != 0)
+            atomicAdd(reinterpret_cast<unsigned long long *>(agg + d.cmp_tile0 + ct0 + tid),
+                      ((unsigned long long)(uint32_t)s_aggc[tid] << 32) | (unsigned long long)(uint32_t)s_aggl[tid]);
+        const int wbase = s_wbase;
+        err |= wbase + to > walk_cap;
+        int e = stripe * walk_cap + wbase + eo;
+        const int lim = (stripe + 1) * walk_cap;
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            if (!((pushm >> j) & 1)) continue;
-            if (e < a.walk_cap) {
-                a.walk[stripe * a.walk_cap + e].mesh = mi;
-                a.walk[stripe * a.walk_cap + e].he = wlist[j];
-            } else {
-                err = true;
+            if (!((openmask >> j) & 1)) continue;
+            if (e < lim) {
+                const int t = base + j * B + tid;
+                walk[e].mesh = mi;
+                walk[e].he = 3 * t + (int)(f[j] & 3u);
             }
             ++e;
         }
+        // the queued turns, one per thread: only the first lanes of the block work
+        const int nq = min(tq, qcap);
+        for (int q = tid; q < nq; q += B) {
+            const int w = s_q[2 * q + 1], sh = w >> 3;
+            const bool nxt = (w & 4) != 0;
+            const int res = run_turn(T, s_q[2 * q], (w & 3) - 1, nxt);
+            err |= res < 0;
+            s_q[2 * q] = res;   // the owner picks it up after the barrier
+            if (nxt && res >= 0 && res == s_tw[sh])
+                tile_tip(s_tip, &s_ntip, tcap, sh, base, rc, tips, cap_tips, d, mi, err);
+        }
+    }
+    // turns beyond the queue (meshes whose polygons are mostly large), in registers
+    for (int step = 0; pend; step++) {
+#pragma unroll
+        for (int k = 0; k < 2 * ITEMS; k++) {
+            if (!((pend >> k) & 1u)) continue;
+            const int r = step < kRotGuard ? turn_step(T, cur[k], lab[k], (k & 1) == 0) : -1;
+            if (r == 0) continue;
+            const int res = r > 0 ? cur[k] : -1;
+            err |= r < 0;
+            const int li = src[k] % 3;
+            if ((k & 1) == 0) {
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    if (i == li) nv3[k >> 1][i] = res;
+                if (res >= 0 && res == s_tw[src[k]])
+                    tile_tip(s_tip, &s_ntip, tcap, src[k], base, rc, tips, cap_tips, d, mi, err);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; i++)
+                    if (i == li) pv3[k >> 1][i] = res;
+            }
+            pend &= ~(1u << k);
+        }
     }
     __syncthreads();
+    // next'/prev' of this lane's triangles, with the queued turns' results
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        const int lt = j * B + tid;
+        if (lt >= cnt) continue;
+#pragma unroll
+        for (int kk = 0; kk < 2; kk++) {
+            const int k = 2 * j + kk;
+            if (qslot[k] < 0) continue;
+            const int res = s_q[2 * qslot[k]], li = src[k] - 3 * lt;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                if (i != li) continue;
+                if (kk == 0)
+                    nv3[j][i] = res;
+                else
+                    pv3[j][i] = res;
+            }
+        }
+        const int h0 = 3 * (base + lt);
+        *reinterpret_cast<GLOBAL v3i *>(nxo + h0) = v3i{nv3[j][0], nv3[j][1], nv3[j][2]};
+        *reinterpret_cast<GLOBAL v3i *>(pvo + h0) = v3i{pv3[j][0], pv3[j][1], pv3[j][2]};
+    }
     // the tile's label and loop bytes in whole words (the label bytes keep
     // their longest-edge bits, which other tiles may be reading)
-    store_bytes_from_lds((gu8)(d.pl) + base, s_pl, cnt, 0xff);
-    store_bytes_from_lds(tflag + base, s_f, cnt, 0x3f);
-    if (tid == 0) {
-        if (one && sh.settled_c)
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.bk.agg + d.cmp_tile0 + ct0),
-                      ((unsigned long long)(uint32_t)sh.settled_c << 32) | (unsigned long long)(uint32_t)sh.settled_l);
-        if (sh.nties) atomicAdd(&d.ctr->nties, sh.nties);
-        const int n = min(sh.ntip, tcap);   // the tile's tips: one append
+    store_bytes_from_lds((gu8)(d.pl) + base, s_pl, cnt);
+    store_bytes_from_lds(tflag + base, s_f, cnt);
+    if (tid == 0) {   // the tile's tips: one append
+        const int n = min(s_ntip, tcap);
         if (n > 0) {
-            const int at = atomicAdd(&a.rc->ntips, n);
+            const int at = atomicAdd(&rc->ntips, n);
             atomicAdd(&d.ctr->ntips, n);
             for (int i = 0; i < n; i++) {
-                if (at + i < a.cap_tips) {
-                    a.tips[at + i].mesh = mi;
-                    a.tips[at + i].he = hb + s_tip[i];
+                if (at + i < cap_tips) {
+                    tips[at + i].mesh = mi;
+                    tips[at + i].he = 3 * base + s_tip[i];
                 } else {
                     err = true;
                 }
             }
         }
     }
-    if (!one && tid <= (base + cnt - 1) / cmp_tb - ct0 && s_aggc[tid] != 0)
-        atomicAdd(reinterpret_cast<unsigned long long *>(a.bk.agg + d.cmp_tile0 + ct0 + tid),
-                  ((unsigned long long)(uint32_t)s_aggc[tid] << 32) | (unsigned long long)(uint32_t)s_aggl[tid]);
     if (err) atomicOr(&d.ctr->err, kErrCorrupt);
 }
 
@@ -947,28 +860,6 @@ __device__ __forceinline__ int wave_reserve2(int32_t *counter, bool pred) {
     return pred ? base + 2 * __popcll(mask & ((1ull << lane) - 1ull)) : -1;
 }
 
-// The middle edge of the tip whose single frontier edge leaves it as a:
-// m = CW^k(a) with k = floor(d/2), d = degree of the tip (CW(e) =
-// next(twin(e))).  Two walkers leave a at once, one clockwise and one
-// counter-clockwise (CCW(e) = twin(prev(e)) = CW^(d-1)(e)); after s steps
-// they stand at CW^s(a) and CW^(d-s)(a), so they meet after about d/2 steps,
-// and where they meet gives d and m.  -1 on a boundary or a runaway turn
-// (tips are interior vertices).
-__device__ __forceinline__ int middle_edge(gcint twin, int a) {
-    int x = a, y = a;   // x = CW^(s-1)(a), y = CW^(d-s+1)(a)
-    for (int s = 1; s <= kRotGuard / 2; s++) {
-        const int gx = twin[x];                 // both loads in flight together
-        const int gy = twin[he_prev(y)];
-        if (gx < 0 || gy < 0) return -1;
-        const int nx = he_next(gx);   // CW^s(a)
-        if (nx == y) return x;        // CW^s(a) = CW^(d-s+1)(a): d = 2s - 1, m = CW^(s-1)(a)
-        if (nx == gy) return nx;      // CW^s(a) = CW^(d-s)(a): d = 2s, m = CW^s(a)
-        x = nx;
-        y = gy;
-    }
-    return -1;
-}
-
 // Middle edge of every barrier tip.  Whole waves take consecutive tips, so the
 // list appends and counters cost one atomic per wave (tips are many on
 // general-position meshes, and atomics on one address serialize).
@@ -990,9 +881,24 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
             const gcint twin = (gcint)d.twin;
             // a: the only frontier edge at the tip v = target(e.he), leaving v
             a = twin[e.he];
-            m = a < 0 ? -1 : middle_edge(twin, a);
-            mt = m < 0 ? -1 : twin[m];
-            if (mt < 0) {
+            bool err = a < 0;
+            int deg = 0, r = a;
+            while (!err) {   // degree: a full clockwise turn around v
+                const int g = twin[r];
+                if (g < 0 || ++deg > kRotGuard) {
+                    err = true;
+                    break;
+                }
+                r = he_next(g);
+                if (r == a) break;
+            }
+            if (!err) {
+                m = a;
+                for (int s2 = 0; s2 < deg / 2; s2++) m = he_next(twin[m]);
+                mt = twin[m];
+                err = mt < 0;
+            }
+            if (err) {
                 atomicOr(&d.ctr->err, kErrCorrupt);
                 ok = false;
             } else {
@@ -1059,142 +965,95 @@ __device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
     return ok;
 }
 
-// Makes LDS writes of one lane visible to the other lanes of its wave.
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Every fix-up anchor o (a half-edge leaving vertex x) gets one wave.  Its
-// first lane gathers the outgoing half-edges around x into LDS, walking
-// clockwise and counter-clockwise from o at once (two loads in flight per
-// step, about degree/2 steps), so that they lie in clockwise order.  Lane p
-// then takes the p-th of them, e_p, and the half-edge entering x before it
-// in the same triangle, p_p = prev(e_p).  With the frontier bits of all of
-// them in two ballots, next'(p_p) is the first frontier e_j at or after p,
-// and prev'(e_p) is prev of the last e_j at or before p whose p_j is
-// frontier (cyclically around an interior vertex; around a boundary vertex
-// both ends are boundary edges, which are frontier).  This is the turn of
-// Section 6.5 for every frontier half-edge at x.  A vertex of degree above
-// 62 is fixed by one lane, edge by edge.
-__global__ void __launch_bounds__(256) k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc,
-                                               const ListEntry *fixes, int cap_fix) {
-    __shared__ int s_rot[4][2 * kWave];   // per wave: counter-clockwise list below kWave, clockwise from it
-    __shared__ int s_hdr[4][4];           // per wave: first, count, closed, overflow
+// Every fix-up anchor o (a half-edge leaving vertex x) gets a group of 32
+// lanes: lane j < 16 takes the outgoing half-edge j clockwise steps from o,
+// lane 16 + k the one k + 1 counter-clockwise steps away (only when the
+// clockwise turn met the boundary, i.e. x is on it), and each lane fixes
+// next'/prev' at its half-edge, so the turns around x run side by side.  The
+// last lane of each side continues past 16 steps on its own.
+__global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *fixes,
+                        int cap_fix) {
     const int nfix = min(rc->nfix, cap_fix);
-    const int lane = __lane_id(), wv = threadIdx.x / kWave;
-    int *rot = s_rot[wv];
-    const int nwaves = gridDim.x * (blockDim.x / kWave);
-    for (int q = blockIdx.x * (blockDim.x / kWave) + wv; q < nfix; q += nwaves) {   // wave-uniform
-        const ListEntry en = fixes[q];
+    const int lane = __lane_id(), gl = lane & 31;
+    const unsigned long long gmask = (lane < 32) ? 0x00000000ffffffffull : 0xffffffff00000000ull;
+    const unsigned long long cwmask = gmask & 0x0000ffff0000ffffull;   // lanes 0-15 of each group
+    const int groups = gridDim.x * (blockDim.x / 32);
+    for (int qb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 2; qb < nfix; qb += groups) {
+        const int q = qb + (lane >> 5);
+        const bool valid = q < nfix;
+        const ListEntry en = valid ? fixes[q] : ListEntry{0, 0};
         const MeshDesc &d = descs[en.mesh];
         const gcint twin = (gcint)d.twin;
         const int o = en.he;
-        if (lane == 0) {
-            int ncw = 1, nccw = 0;
-            bool closed = false, over = false, cw = true, ccw = true;
-            rot[kWave] = o;
-            int x = o, y = o;   // the last half-edge each walker added
-            for (int s = 0; (cw || ccw) && s < kRotGuard; s++) {
-                const int gx = cw ? twin[x] : 0;
-                const int gy = ccw ? twin[he_prev(y)] : 0;
-                cw = cw && gx >= 0;    // x has no twin: it is the clockwise-most
-                ccw = ccw && gy >= 0;  // prev(y) has no twin: y is the counter-clockwise-most
-                const int nx = cw ? he_next(gx) : -1;
-                if (cw && nx == y) {   // around an interior vertex: every edge listed
-                    closed = true;
+        bool ok = true, have = false, boundary = false;
+        int e = o;
+        if (valid && gl < 16) {   // clockwise: e <- next(twin(e)), gl steps
+            have = true;
+            for (int s2 = 0; s2 < gl; s2++) {
+                const int g = twin[e];
+                if (g < 0) {
+                    boundary = true;
+                    have = false;
                     break;
                 }
-                if (cw && ccw && nx == gy) {   // both walkers reach the same edge
-                    if (ncw + nccw + 1 > kWave - 2) {
-                        over = true;
-                        break;
-                    }
-                    rot[kWave + ncw++] = nx;
-                    closed = true;
+                e = he_next(g);
+                if (e == o) {   // around a closed fan in fewer steps: no edge of its own
+                    have = false;
                     break;
                 }
-                if (ncw + nccw + 2 > kWave - 2) {
-                    over = cw || ccw;
-                    break;
-                }
-                if (cw) {
-                    rot[kWave + ncw++] = nx;
-                    x = nx;
-                }
-                if (ccw) {
-                    rot[kWave - 1 - nccw++] = gy;
-                    y = gy;
-                }
-            }
-            s_hdr[wv][0] = kWave - nccw;
-            s_hdr[wv][1] = ncw + nccw;
-            s_hdr[wv][2] = closed;
-            s_hdr[wv][3] = over || (!closed && (cw || ccw));   // a runaway turn also takes the slow path
-        }
-        wave_sync_lds();
-        const int first = s_hdr[wv][0], n = s_hdr[wv][1];
-        const bool closed = s_hdr[wv][2] != 0, over = s_hdr[wv][3] != 0;
-        bool ok = true;
-        if (over) {
-            // a vertex of very high degree: one lane turns around it, edge by
-            // edge, clockwise from o and (at a boundary vertex) back the other way
-            if (lane == 0) {
-                int e = o;
-                bool boundary = false;
-                for (int s = 0; s < kRotGuard; s++) {
-                    ok &= fix_around(d, e);
-                    const int g = twin[e];
-                    if (g < 0) {
-                        boundary = true;
-                        break;
-                    }
-                    e = he_next(g);
-                    if (e == o) break;
-                }
-                if (boundary) {
-                    e = o;
-                    for (int s = 0; s < kRotGuard; s++) {
-                        const int g = twin[he_prev(e)];
-                        if (g < 0) break;
-                        e = g;
-                        ok &= fix_around(d, e);
-                    }
-                }
-            }
-        } else {
-            const bool valid = lane < n;
-            const int e = valid ? rot[first + lane] : 0;
-            const int te = tri_of(e), le = e - 3 * te;
-            const int lp = le == 0 ? 2 : le - 1;
-            const uint32_t tf = valid ? ((gcu8)d.tflag)[te] : 0u;
-            const bool Fe = valid && fbit(tf, le), Fp = valid && fbit(tf, lp);
-            const unsigned long long mE = __ballot(Fe), mP = __ballot(Fp);
-            // next'(p_p): the first frontier e_j with j >= p
-            const unsigned long long ge = mE & (~0ull << lane);
-            int jn = ge ? __ffsll((long long)ge) - 1 : (closed && mE ? __ffsll((long long)mE) - 1 : -1);
-            // prev'(e_p): prev of the last e_j with j <= p whose p_j is frontier
-            const unsigned long long le2 = mP & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-            int jp = le2 ? 63 - __clzll((long long)le2) : (closed && mP ? 63 - __clzll((long long)mP) : -1);
-            const int en_ = __shfl(e, jn < 0 ? 0 : jn);
-            const int ep_ = __shfl(e, jp < 0 ? 0 : jp);
-            if (Fp) {
-                ok &= jn >= 0;
-                d.next_o[3 * te + lp] = jn >= 0 ? en_ : -1;
-            }
-            if (Fe) {
-                ok &= jp >= 0;
-                d.prev_o[e] = jp >= 0 ? he_prev(ep_) : -1;
             }
         }
-        if (!ok) atomicOr(&d.ctr->err, kErrCorrupt);
-        wave_sync_lds();   // the first lane overwrites the lists for the next anchor
+        // past 16 steps clockwise: the last lane goes on alone (and finds the
+        // boundary if the turn reaches it there)
+        if (have && gl == 15) {
+            int f = e;
+            for (int steps = 0;; steps++) {
+                const int g = twin[f];
+                if (g < 0) {
+                    boundary = true;
+                    break;
+                }
+                f = he_next(g);
+                if (f == o) break;
+                if (steps > kRotGuard) {
+                    ok = false;
+                    break;
+                }
+                ok &= fix_around(d, f);
+            }
+        }
+        const bool open = (__ballot(boundary) & cwmask & gmask) != 0ull;
+        if (valid && gl >= 16 && open) {   // counter-clockwise: e <- twin(prev(e)), gl - 15 steps
+            have = true;
+            for (int s2 = 0; s2 <= gl - 16; s2++) {
+                const int g = twin[he_prev(e)];
+                if (g < 0) {
+                    have = false;
+                    break;
+                }
+                e = g;
+            }
+        }
+        if (have) ok &= fix_around(d, e);
+        // past 16 steps counter-clockwise: the last lane goes on alone
+        if (have && gl == 31) {
+            for (int steps = 0;; steps++) {
+                const int g = twin[he_prev(e)];
+                if (g < 0) break;
+                e = g;
+                if (steps > kRotGuard) {
+                    ok = false;
+                    break;
+                }
+                ok &= fix_around(d, e);
+            }
+        }
+        if (valid && !ok) atomicOr(&d.ctr->err, kErrCorrupt);
     }
 }
 
 // ---------------------------------------------------------------------------
-// k_walk: seed -> frontier half-edge -> the loop, from both ends at once
+// k_walk: seed -> frontier half-edge -> loop minimum and length
 // ---------------------------------------------------------------------------
 
 // From seed s, turn clockwise around origin(s) until a frontier half-edge.
@@ -1209,151 +1068,192 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
     return -1;
 }
 
-struct WalkArgs {
-    const MeshDesc *descs;
-    const ListEntry *walk;
-    const int32_t *walk_counts;
-    int walk_cap;
-    Buckets bk;
-};
 
-// Every entry of the walk list: a frontier half-edge on a loop (or, as ~s, a
-// seed s whose triangle has none: turn to one first).  Each lane walks its
-// loop forward along next' and backward along prev' at once, so the two
-// loads of a step are in flight together and a loop of L half-edges takes
-// about L/2 steps; both ends are recorded in LDS.  When the ends meet, the
-// loop's minimum and length are known: the byte at the minimum's triangle
-// records them, and the loop goes to the bucket of the minimum's compaction
-// tile, starting at its minimum, so k_compact places it without walking it
-// again.  After a repair several seeds can walk one loop; in a mesh with
-// tips every walker ORs the same byte in and only the one that found it
-// empty counts and stores the loop.
-__global__ void __launch_bounds__(256) k_walk(WalkArgs w) {
+// Every entry of the walk list: from the seed to a frontier half-edge of its
+// polygon (a frontier half-edge of the seed's own triangle if it has one),
+// around the loop, and the loop recorded.  Each thread keeps ITEMS loops in
+// flight and advances them in lock-step; each loop's next' array and bound
+// sit in registers.  Every chain also writes the half-edges it visits to an
+// LDS buffer, so the walker that claims a loop of at most BUF half-edges
+// copies it to the scratch pool (rotation index of the minimum, then the
+// half-edges in walk order) and k_compact places it without walking it
+// again.  Whole waves iterate together: the pool is reserved once per wave
+// and step, for every loop that closed in that step and fits the buffer,
+// while the claims are still in flight (a walker that loses the claim leaves
+// its space unused).
+template <int ITEMS, int BUF>
+__global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
+                                              const int32_t *walk_counts, int walk_cap, uint64_t *agg,
+                                              int cmp_tb, int32_t *wbuf, int32_t *wbuf_counts, int wbuf_cap) {
+    constexpr int kSlots = 256 * ITEMS;
     __shared__ int s_pref[kStripes + 1];
-    __shared__ int s_fw[kWalkBuf * 256], s_bw[kWalkBuf * 256];   // element k of lane tid at k * 256 + tid
-    const int total = striped_prefix(w.walk_counts, w.walk_cap, s_pref);
-    const int nthreads = gridDim.x * blockDim.x, tid = threadIdx.x;
-    for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += nthreads) {   // block-uniform
-        const int gi = g0 + tid;
-        int mesh = 0, start = -1;
-        bool bad = false;
-        if (gi < total) {
-            const ListEntry e = w.walk[striped_index(s_pref, w.walk_cap, gi)];
-            mesh = e.mesh;
-            start = e.he >= 0 ? e.he : seek_frontier(w.descs[mesh], ~e.he);
-            bad = start < 0;
-        }
-        const MeshDesc &d = w.descs[mesh];
-        const gcint nx = (gcint)d.next_o, pv = (gcint)d.prev_o;
-        const int lim = 3 * d.nt;
-        int f = start, b = start, mn = start, k = 0, L = 0;
-        bool act = start >= 0;
-        if (act) s_fw[tid] = start;
-        while (act) {
-            ++k;
-            const int nf = nx[f], nb = pv[b];   // both in flight together
-            if (nf < 0 || nb < 0 || 2 * k > lim + 2) {
-                bad = true;
-                break;
+    __shared__ int s_buf[BUF * kSlots];   // element k of chain slot q at k * kSlots + q
+    const int total = striped_prefix(walk_counts, walk_cap, s_pref);
+    const int nthreads = gridDim.x * blockDim.x;
+    const int lane = __lane_id(), tid = threadIdx.x;
+    const int wstripe = ((blockIdx.x * blockDim.x + tid) >> 6) % kStripes;   // this wave's pool stripe
+    for (int b0 = blockIdx.x * blockDim.x; b0 < total; b0 += nthreads * ITEMS) {   // block-uniform
+        gcint nx[ITEMS];
+        int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], rot[ITEMS], len[ITEMS], lim[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            start[j] = cur[j] = mn[j] = -1;
+            rot[j] = len[j] = lim[j] = 0;
+            mesh[j] = 0;
+            nx[j] = nullptr;
+            const int g = b0 + tid + j * nthreads;
+            if (g >= total) continue;
+            const ListEntry e = walk[striped_index(s_pref, walk_cap, g)];
+            const MeshDesc &d = descs[e.mesh];
+            mesh[j] = e.mesh;
+            nx[j] = (gcint)d.next_o;
+            lim[j] = 3 * d.nt;
+            const int t = tri_of(e.he);
+            const uint32_t f = ((gcu8)d.tflag)[t];
+            int st = fbit(f, e.he - 3 * t) ? e.he : -1;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                if (st < 0 && fbit(f, i)) st = 3 * t + i;
+            if (st < 0) st = seek_frontier(d, e.he);
+            if (st < 0) {
+                atomicOr(&d.ctr->err, kErrCorrupt);
+                continue;
             }
-            if (nf == b) {   // forward reached the backward end: L = 2k - 1
-                L = 2 * k - 1;
-                break;
-            }
-            mn = nf < mn ? nf : mn;
-            if (k < kWalkBuf) s_fw[k * 256 + tid] = nf;
-            if (nf == nb) {   // both ends reached the same half-edge: L = 2k
-                L = 2 * k;
-                break;
-            }
-            mn = nb < mn ? nb : mn;
-            if (k < kWalkBuf) s_bw[k * 256 + tid] = nb;
-            f = nf;
-            b = nb;
+            start[j] = cur[j] = mn[j] = st;
         }
-        if (bad) atomicOr(&d.ctr->err, kErrCorrupt);
-        if (L <= 0) continue;
-        // the loop in next' order from start: nfw forward entries, then the
-        // backward ones in reverse
-        const int nfw = (L & 1) ? (L + 1) / 2 : L / 2 + 1;
-        const bool keep = nfw <= kWalkBuf;
-        auto seq = [&](int i) { return i < nfw ? s_fw[i * 256 + tid] : s_bw[(L - i) * 256 + tid]; };
-        const uint32_t code = loop_code(mn, L);
-        const int tm = tri_of(mn);
-        bool won = true;
-        if (d.ctr->ntips > 0) {
-            uint32_t *wd = reinterpret_cast<uint32_t *>(d.pl) + (tm >> 2);
-            const uint32_t old = atomicOr(wd, code << (8 * (tm & 3)));
-            won = ((old >> (8 * (tm & 3))) & 0xffu) == 0u;
-        } else {
-            ((gu8)d.pl)[tm] = (uint8_t)code;   // one walker per loop without a repair
-        }
-        if (!won) continue;
-        agg_add(w.bk, d, mn, L);
-        if (keep) {
-            int rot = 0;
-            for (int i = 0; i < L; i++)
-                if (seq(i) == mn) rot = i;
-            bucket_put(w.bk, d, mn, L, [&](int i) { return seq(i + rot < L ? i + rot : i + rot - L); });
+        while (true) {
+            bool active = false;
+            int need[ITEMS];
+            bool closed[ITEMS];
+            uint32_t claim[ITEMS];
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                need[j] = 0;
+                closed[j] = false;
+                claim[j] = 0;
+                if (start[j] < 0) continue;
+                if (len[j] < BUF) s_buf[len[j] * kSlots + j * 256 + tid] = cur[j];
+                if (cur[j] < mn[j]) {
+                    mn[j] = cur[j];
+                    rot[j] = len[j];
+                }
+                ++len[j];
+                cur[j] = nx[j][cur[j]];
+                if (cur[j] < 0 || len[j] > lim[j]) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    start[j] = -1;
+                    continue;
+                }
+                if (cur[j] == start[j]) {
+                    closed[j] = true;
+                    claim[j] = claim_issue(descs[mesh[j]], mn[j], len[j]);
+                    // whole 16-byte groups, so k_compact reads a loop with vector loads
+                    need[j] = len[j] <= BUF ? (len[j] + 4) & ~3 : 0;
+                    start[j] = -1;
+                    continue;
+                }
+                active = true;
+            }
+            // pool space for the loops claimed in this step: one atomic per wave
+            int mine = 0;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) mine += need[j];
+            const int incl = wave_incl_scan(mine);   // the loop's exit is wave-uniform: all lanes here
+            const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+            int wbase = 0;
+            if (lane == 0 && wtot > 0) wbase = atomicAdd(&wbuf_counts[wstripe * kStripePad], wtot);
+            wbase = __builtin_amdgcn_readlane(wbase, 0);
+            const bool room = wbase + wtot <= wbuf_cap;
+            int pos = wstripe * wbuf_cap + wbase + incl - mine;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if (!closed[j]) continue;
+                const MeshDesc &d = descs[mesh[j]];
+                const bool won = claim_won(d, claim[j], mn[j], len[j], agg, cmp_tb);
+                if (won && need[j] && room) {
+                    const gint out = (gint)wbuf + pos;
+                    out[0] = rot[j];
+                    for (int k = 0; k < len[j]; k++) out[1 + k] = s_buf[k * kSlots + j * 256 + tid];
+                    const int tm = tri_of(mn[j]);
+                    ((gint)d.lpos)[tm] = pos;
+                    atomicOr(reinterpret_cast<uint32_t *>(d.tflag) + (tm >> 2), kStoredBit << (8 * (tm & 3)));
+                }
+                pos += need[j];
+            }
+            if (!__any(active)) break;
         }
     }
 }
 
-// The loops k_compact left out (no kernel stored them): each written from
-// its minimum at its offset, forward along next' and backward along prev' at
-// once (the length is known).
+// The loops k_compact left out: each written from its minimum at its offset.
+template <int ITEMS>
 __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs, const EmitEntry *emit,
                                               const int32_t *emit_counts, int emit_cap) {
     __shared__ int s_pref[kStripes + 1];
     const int total = striped_prefix(emit_counts, emit_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += nthreads) {
-        const EmitEntry e = emit[striped_index(s_pref, emit_cap, g)];
-        const MeshDesc &d = descs[e.mesh];
-        const gcint nx = (gcint)d.next_o, pv = (gcint)d.prev_o;
-        const gint out = (gint)d.loop_he;
-        const int len = e.len, off = e.off;
-        if (len <= 0 || off < 0 || off + len > 3 * d.nt) {
-            atomicOr(&d.ctr->err, kErrCorrupt);
-            continue;
+    for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
+        gcint nx[ITEMS];
+        gint out[ITEMS];
+        int mesh[ITEMS], cur[ITEMS], mn[ITEMS], pos[ITEMS], lim[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            cur[j] = -1;
+            mesh[j] = mn[j] = pos[j] = lim[j] = 0;
+            nx[j] = nullptr;
+            out[j] = nullptr;
+            const int g = g0 + j * nthreads;
+            if (g >= total) continue;
+            const EmitEntry e = emit[striped_index(s_pref, emit_cap, g)];
+            const MeshDesc &d = descs[e.mesh];
+            mesh[j] = e.mesh;
+            nx[j] = (gcint)d.next_o;
+            out[j] = (gint)d.loop_he;
+            cur[j] = mn[j] = e.mn;
+            pos[j] = e.off;
+            lim[j] = 3 * d.nt;
         }
-        out[off] = e.mn;
-        int f = e.mn, b = e.mn;
-        bool ok = true;
-        const int nfw = len / 2, nbw = (len - 1) / 2;
-        for (int i = 1; i <= nfw && ok; i++) {
-            f = nx[f];
-            int bb = b;
-            if (i <= nbw) bb = pv[b];
-            if (f < 0 || bb < 0) {
-                ok = false;
-                break;
-            }
-            out[off + i] = f;
-            if (i <= nbw) {
-                b = bb;
-                out[off + len - i] = b;
+        bool active = true;
+        while (active) {
+            active = false;
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                if (cur[j] < 0) continue;
+                if (pos[j] >= lim[j]) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    cur[j] = -1;
+                    continue;
+                }
+                out[j][pos[j]++] = cur[j];
+                cur[j] = nx[j][cur[j]];
+                if (cur[j] < 0) {
+                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
+                    continue;
+                }
+                if (cur[j] == mn[j]) {
+                    cur[j] = -1;
+                    continue;
+                }
+                active = true;
             }
         }
-        // the two ends must join: next' of the last forward half-edge is the
-        // last backward one (or the minimum itself)
-        if (!ok || nx[f] != b) atomicOr(&d.ctr->err, kErrCorrupt);
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_tile_scan: exclusive scan of the compaction tiles' loop totals
 //
-// k_relink and k_walk add every loop, once, to the total of the compaction
-// tile holding its minimum: (loops << 32 | half-edges).  Per mesh, blocks of
-// kScanChunk tiles turn the totals into exclusive prefixes within their
-// chunk, and the last block to finish scans the chunk totals and records the
-// mesh's polygon and loop half-edge counts, so each k_compact tile starts
-// with its output offsets known.
+// k_relink (settled loops) and k_walk (walked loops) add every loop, once, to
+// the total of the compaction tile holding its minimum: (loops << 32 |
+// half-edges).  One block per mesh turns the totals into exclusive prefixes
+// in place and records the mesh's polygon and loop half-edge counts, so each
+// k_compact tile starts with its output offsets known.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__ descs, uint64_t *status,
                                                      uint64_t *cpre, int cmp_tb) {
+    // block (mesh, chunk): tiles [chunk * kScanChunk, ...) of that mesh, one
+    // per thread, read and written contiguously
     __shared__ int s_scan[72];
     __shared__ int s_last;
     const MeshDesc &d = descs[blockIdx.x];
@@ -1417,21 +1317,12 @@ __device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
     return len;
 }
 
-struct CompactArgs {
-    const MeshDesc *descs;
-    int nmesh;
-    const uint64_t *status;
-    const uint64_t *cpre;
-    EmitEntry *emit;
-    int32_t *emit_counts;
-    int emit_cap;
-    const int32_t *bcnt;
-    const int32_t *bucket;
-    int bucket_cap;
-};
-
 template <int ITEMS>
-__global__ void __launch_bounds__(1024) k_compact(CompactArgs c) {
+__global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
+                                                  const uint64_t *status, const uint64_t *cpre, EmitEntry *emit,
+                                                  int32_t *emit_counts, int emit_cap, const int32_t *wbuf) {
+    // LDS: loop half-edges (compact_he_cap of them), seeds and local offsets
+    // (one per triangle)
     extern __shared__ int4 lds_raw[];
     const int B = blockDim.x, tid = threadIdx.x;
     const int TB = B * ITEMS;
@@ -1439,195 +1330,181 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs c) {
     int *s_he = reinterpret_cast<int *>(lds_raw);
     int *s_seed = s_he + he_cap;
     int *s_off = s_seed + TB;
-    int *s_bk = s_off + TB;                                            // first ints of the bucket
-    int16_t *s_rec = reinterpret_cast<int16_t *>(s_bk + kBucketStage);   // record of each triangle's loop
     __shared__ int s_scan[72];
     __shared__ int s_ebase;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int mi = find_mesh<2>(c.descs, c.nmesh, tile);
-    const MeshDesc &d = c.descs[mi];
+    const int mi = find_mesh<2>(descs, nmesh, tile);
+    const MeshDesc &d = descs[mi];
     const int nt = d.nt, nh = 3 * nt;
     const int ltile = tile - d.cmp_tile0;
     const int mesh_tiles = nt > 0 ? (nt + TB - 1) / TB : 1;
-    const int l0 = tid * ITEMS, t0 = ltile * TB + l0;
+    const int t0 = ltile * TB + tid * ITEMS;
     const gcint nx = (gcint)d.next_o;
     const gcu8 plb = (gcu8)d.pl, tfl = (gcu8)d.tflag;
-    const gcint bkt = (gcint)c.bucket + (size_t)tile * c.bucket_cap;
-    const int stage = min(c.bucket_cap, kBucketStage);
-
-    // 1. everything this tile reads, issued together: its prefix, its bucket
-    //    (count and first ints), and the loop and label bytes of this
-    //    thread's ITEMS contiguous triangles
-    const uint64_t pre = c.status[tile] + c.cpre[d.cmp_tile0 + ltile / kScanChunk * kScanChunk];
+    // prefix within the chunk plus the chunk's prefix (no field carries)
+    const uint64_t pre = status[tile] + cpre[d.cmp_tile0 + ltile / kScanChunk * kScanChunk];
     const int pc = (int)(pre >> 32), ps = (int)(uint32_t)pre;
-    const int nb = min(c.bcnt[tile], c.bucket_cap);
-    constexpr int kStagePer = (kBucketStage + 63) / 64;
-    int bv[kStagePer];
-#pragma unroll
-    for (int p = 0; p < kStagePer; p++) {
-        const int k = tid + p * B;
-        bv[p] = k < stage ? bkt[k] : 0;
-    }
+
+    // 1. loop minima and lengths of this thread's ITEMS contiguous triangles;
+    //    which loops are longer than a quad, and which of those k_walk stored
+    //    (the rest k_emit writes)
+    //    (the walk-pool positions come with them, read whether or not a loop
+    //    was stored there, so a stored loop's pool read follows directly)
     uint8_t code[ITEMS], fl[ITEMS];
+    int lp[ITEMS];
+    const gcint lpos = (gcint)d.lpos;
     if (ITEMS == 4 && t0 + 4 <= nt) {
         const uint32_t w = *reinterpret_cast<GLOBAL const uint32_t *>(plb + t0);
         const uint32_t v = *reinterpret_cast<GLOBAL const uint32_t *>(tfl + t0);
+        const v4i l4 = *(GLOBAL const v4i *)(lpos + t0);
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             code[j] = (uint8_t)(w >> (8 * (j & 3)));
             fl[j] = (uint8_t)(v >> (8 * (j & 3)));
         }
+        lp[0] = l4.x;
+        lp[1 % ITEMS] = l4.y;
+        lp[2 % ITEMS] = l4.z;
+        lp[3 % ITEMS] = l4.w;
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             code[j] = t0 + j < nt ? plb[t0 + j] : 0;
             fl[j] = t0 + j < nt ? tfl[t0 + j] : 0;
+            lp[j] = t0 + j < nt ? lpos[t0 + j] : 0;
         }
     }
-#pragma unroll
-    for (int p = 0; p < kStagePer; p++) {
-        const int k = tid + p * B;
-        if (k < stage) s_bk[k] = bv[p];
-    }
-#pragma unroll
-    for (int j = 0; j < ITEMS; j++) s_rec[l0 + j] = -1;
-    __syncthreads();
-    // 2. the bucket's records: each header names the local triangle of its
-    //    loop's minimum
-    for (int k = tid; k < nb; k += B) {
-        const int v = k < stage ? s_bk[k] : bkt[k];
-        if (v < 0) {
-            const int lt = (v >> 16) & 0x7fff;
-            if (lt < TB) s_rec[lt] = (int16_t)k;
-        }
-    }
-    __syncthreads();
-    // 3. loop lengths; the loops whose half-edges come from neither the bytes
-    //    nor the bucket go to k_emit
-    int lens[ITEMS], rec[ITEMS];
-    bool toemit[ITEMS];
+    int lens[ITEMS];
+    bool defer[ITEMS];
     int cnt = 0, sum = 0, nd = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         lens[j] = 0;
-        toemit[j] = false;
-        rec[j] = s_rec[l0 + j];
+        defer[j] = false;
         if (!code[j]) continue;
-        int len = code_len(code[j]);
+        int len = code[j] >> 2;
+        if (len == kPlQuadNext) len = 4;
         if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
         if (len <= 0) {
             bad = true;
             len = 0;
         }
         lens[j] = len;
-        // loops of three and two-triangle loops of four are written from the
-        // bytes; the rest from their bucket record, else by k_emit
-        const bool quad = len == 4 && __popc((fl[j] >> 2) & 7u) == 2;
-        toemit[j] = len > 0 && len != 3 && (code[j] >> 2) != kPlQuadNext && rec[j] < 0 && !quad;
+        // loops of three and two-triangle loops of four are written here
+        defer[j] = len > 0 && len != 3 && !(len == 4 && __popc((fl[j] >> 2) & 7u) == 2);
         cnt += 1;
         sum += len;
-        nd += toemit[j];
+        nd += defer[j] && !(fl[j] & kStoredBit);
     }
-    // 4. block scan: tile-local loop index and offset, emit-list slot
+    // 2. block scan: tile-local loop index and offset, emit-list slot
     int ecn, esum, tcn, tsum;
     block_excl_scan2(cnt | (nd << 16), sum, ecn, esum, tcn, tsum, s_scan);
     const int tcnt = tcn & 0xffff, tnd = tcn >> 16;
     const int stripe = tile % kStripes;
     if (tid == 0) {
-        s_ebase = tnd > 0 ? atomicAdd(&c.emit_counts[stripe * kStripePad], tnd) : 0;
+        s_ebase = tnd > 0 ? atomicAdd(&emit_counts[stripe * kStripePad], tnd) : 0;
         // the tiles' prefixes must add up to the mesh totals
         if (ltile == mesh_tiles - 1 && (pc + tcnt != d.ctr->npoly || ps + tsum != d.ctr->nloop)) bad = true;
     }
     const bool fits = tsum <= he_cap && pc + tcnt <= nt && ps + tsum <= nh;
-    // 5. seeds, local offsets and loops; into LDS, or straight to global
+    // 3. seeds, local offsets and loops; into LDS, or straight to global
     //    memory for a tile whose loops do not fit
     // A loop of 3 is one triangle: (mn, next, prev).  A loop of 4 is two
     // triangles: the minimum's triangle has frontier half-edges a, b = next(a)
     // and crosses to the other triangle at b, whose two frontier half-edges
-    // follow as p1 = next'(b), next(p1).
+    // follow as p1 = next'(b), next(p1).  Longer loops get their offset here
+    // and are written by k_emit.
     __syncthreads();
-    const int elim = (stripe + 1) * c.emit_cap;
-    bad |= s_ebase + tnd > c.emit_cap;
+    const int elim = (stripe + 1) * emit_cap;
+    bad |= s_ebase + tnd > emit_cap;
     // the body is instantiated twice: loops into LDS (the tile fits, the
     // usual case), or straight to global memory; the tile decides for all
     // its threads
     auto place_loops = [&](auto he_out) {
-        int q = ecn & 0xffff, off = esum, e = (ecn >> 16) + stripe * c.emit_cap + s_ebase;
+    int q = ecn & 0xffff, off = esum, e = (ecn >> 16) + stripe * emit_cap + s_ebase;
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            if (!code[j]) continue;
-            const int t = t0 + j;
-            const uint32_t fb = (fl[j] >> 2) & 7u;
-            const bool qn = (code[j] >> 2) == kPlQuadNext;
-            const int mn = 3 * t + (qn ? __builtin_ctz(fb | 8u) : (code[j] & 3));
-            const int len = lens[j];
-            const bool place = fits || (pc + q < nt && ps + off + len <= nh);
-            if (!place) {
-                bad = true;
+    for (int j = 0; j < ITEMS; j++) {
+        if (!code[j]) continue;
+        const int t = t0 + j;
+        const uint32_t fb = (fl[j] >> 2) & 7u;
+        const bool qn = (code[j] >> 2) == kPlQuadNext;
+        const int mn = 3 * t + (qn ? __builtin_ctz(fb | 8u) : (code[j] & 3));
+        const bool place = fits || (pc + q < nt && ps + off + lens[j] <= nh);
+        if (!place) {
+            bad = true;
+        } else {
+            if (fits) {
+                s_seed[q] = mn;
+                s_off[q] = off;
             } else {
-                if (fits) {
-                    s_seed[q] = mn;
-                    s_off[q] = off;
-                } else {
-                    d.seeds[pc + q] = mn;
-                    d.loop_off[pc + q] = ps + off;
-                }
-                if (len == 3) {
-                    he_out[off] = mn;
-                    he_out[off + 1] = he_next(mn);
-                    he_out[off + 2] = he_prev(mn);
-                } else if (qn || (len == 4 && rec[j] < 0 && !toemit[j])) {
-                    // non-frontier edge sx; a = next(sx), b = prev(sx); the loop
-                    // crosses sx's twin into the other triangle
-                    const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
-                    const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
-                    int p1;
-                    if (qn) {   // the second triangle is t + 1: next'(b) leaves its terminal edge
-                        const int Lp = code[j] & 3;
-                        p1 = 3 * (t + 1) + (Lp == 2 ? 0 : Lp + 1);
-                    } else {
-                        p1 = nx[bb];
-                    }
-                    if (p1 < 0 || (mn != aa && mn != bb)) {
-                        bad = true;
-                    } else if (mn == aa) {
-                        he_out[off] = aa;
-                        he_out[off + 1] = bb;
-                        he_out[off + 2] = p1;
-                        he_out[off + 3] = he_next(p1);
-                    } else {
-                        he_out[off] = bb;
-                        he_out[off + 1] = p1;
-                        he_out[off + 2] = he_next(p1);
-                        he_out[off + 3] = aa;
-                    }
-                } else if (rec[j] >= 0) {
-                    // stored from its minimum by the kernel that walked it
-                    const int k0 = rec[j];
-                    const int hdr = k0 < stage ? s_bk[k0] : bkt[k0];
-                    if ((hdr & 0xffff) != len || k0 + 1 + len > nb) {
-                        bad = true;
-                    } else {
-                        for (int i = 0; i < len; i++) {
-                            const int k = k0 + 1 + i;
-                            he_out[off + i] = k < stage ? s_bk[k] : bkt[k];
-                        }
-                        bad |= (k0 + 1 < stage ? s_bk[k0 + 1] : bkt[k0 + 1]) != mn;
-                    }
-                } else {
-                    if (e < elim) {
-                        c.emit[e].mesh = mi;
-                        c.emit[e].mn = mn;
-                        c.emit[e].off = ps + off;
-                        c.emit[e].len = len;
-                    }
-                    ++e;
-                }
+                d.seeds[pc + q] = mn;
+                d.loop_off[pc + q] = ps + off;
             }
-            ++q;
-            off += len;
+            if (lens[j] == 3) {
+                he_out[off] = mn;
+                he_out[off + 1] = he_next(mn);
+                he_out[off + 2] = he_prev(mn);
+            } else if (!defer[j] && lens[j] == 4) {
+                // non-frontier edge sx; a = next(sx), b = prev(sx); the loop
+                // crosses sx's twin into the other triangle
+                const int sx = (fb & 1u) == 0 ? 0 : ((fb & 2u) == 0 ? 1 : 2);
+                const int aa = 3 * t + (sx == 2 ? 0 : sx + 1), bb = 3 * t + (sx == 0 ? 2 : sx - 1);
+                int p1;
+                if (qn) {   // the second triangle is t + 1: next'(b) leaves its terminal edge
+                    const int Lp = code[j] & 3;
+                    p1 = 3 * (t + 1) + (Lp == 2 ? 0 : Lp + 1);
+                } else {
+                    p1 = nx[bb];
+                }
+                if (p1 < 0 || (mn != aa && mn != bb)) {
+                    bad = true;
+                } else if (mn == aa) {
+                    he_out[off] = aa;
+                    he_out[off + 1] = bb;
+                    he_out[off + 2] = p1;
+                    he_out[off + 3] = he_next(p1);
+                } else {
+                    he_out[off] = bb;
+                    he_out[off + 1] = p1;
+                    he_out[off + 2] = he_next(p1);
+                    he_out[off + 3] = aa;
+                }
+            } else if (defer[j] && (fl[j] & kStoredBit)) {
+                // stored by k_walk in walk order from some start; rotate so
+                // the loop begins at its minimum (loads first, all in flight)
+                static_assert(kWalkBuf % 4 == 0, "stored loops are read in 16-byte groups");
+                const int len = lens[j];
+                const GLOBAL v4i *src = (GLOBAL const v4i *)((gcint)wbuf + lp[j]);
+                v4i g[kWalkBuf / 4 + 1];   // rotation index, then the half-edges
+#pragma unroll
+                for (int c = 0; c <= kWalkBuf / 4; c++) g[c] = src[c];
+                int v[kWalkBuf + 4];
+#pragma unroll
+                for (int c = 0; c <= kWalkBuf / 4; c++) {
+                    v[4 * c] = g[c].x;
+                    v[4 * c + 1] = g[c].y;
+                    v[4 * c + 2] = g[c].z;
+                    v[4 * c + 3] = g[c].w;
+                }
+                const int rot = v[0];
+                if (rot < 0 || rot >= len || len > kWalkBuf || v[1 + rot] != mn) bad = true;
+                else
+#pragma unroll
+                    for (int k = 0; k < kWalkBuf; k++)
+                        if (k < len) he_out[off + (k >= rot ? k - rot : k - rot + len)] = v[1 + k];
+            } else if (defer[j]) {
+                if (e < elim) {
+                    emit[e].mesh = mi;
+                    emit[e].mn = mn;
+                    emit[e].off = ps + off;
+                }
+                ++e;
+            }
         }
+        ++q;
+        off += lens[j];
+    }
     };
     if (fits)
         place_loops(s_he);
@@ -1637,7 +1514,7 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs c) {
         __syncthreads();
         // contiguous stores of the tile's part of seeds, loop_off, loop_he;
         // all of a thread's LDS reads are issued before its first store
-        constexpr int kSeedIt = ITEMS;                          // tcnt <= TB
+        constexpr int kSeedIt = ITEMS;                  // tcnt <= TB
         constexpr int kHeIt = (kCompactHe4 * ITEMS + 3) / 4;   // tsum <= he_cap
         const gint seeds = (gint)d.seeds, loff = (gint)d.loop_off, lhe = (gint)d.loop_he;
         int vs[kSeedIt], vo[kSeedIt], vh[kHeIt];
@@ -1740,24 +1617,26 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     if (rb.nmesh <= 0) return hipSuccess;
     const int pb = cfg.persistent_blocks, pt = cfg.block_persistent;
     const int cmp_tb = cfg.block_compact * cfg.items_compact;   // triangles per compaction tile
-    const Buckets bk = {rb.status, rb.bcnt, rb.bucket, rb.bucket_cap, cmp_tb};
+
+    H(K_INIT, 0);
+    {
+        int n = rb.cmp_tiles > rb.nmesh ? rb.cmp_tiles : rb.nmesh;
+        int grid = (n + 255) / 256;
+        grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
+        hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, rb.rc, rb.ctrs, rb.nmesh, rb.status,
+                           rb.cmp_tiles, rb.walk_counts, rb.emit_counts, rb.wbuf_counts);
+    }
+    H(K_INIT, 1);
 
     H(K_LABEL, 0);
-    {
-        const ClearArgs ca = {rb.rc, rb.ctrs, rb.nmesh, rb.status, rb.bcnt, rb.cmp_tiles, rb.walk_counts,
-                              rb.emit_counts};
-        GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label),
-                        sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh, ca);
-    }
+    GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label),
+                    sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh);
     H(K_LABEL, 1);
 
     H(K_RELINK, 0);
-    {
-        const RelinkArgs ra = {rb.descs, rb.nmesh, rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts,
-                               rb.walk_cap, bk};
-        GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                        (sizeof(int) * 6 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, ra);
-    }
+    GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
+                    (sizeof(int) * 3 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
+                    rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, rb.status, cmp_tb);
     H(K_RELINK, 1);
 
     H(K_REPAIR, 0);
@@ -1766,14 +1645,12 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_REPAIR, 1);
 
     H(K_FIXUP, 0);
-    hipLaunchKernelGGL(k_fixup, dim3(pb), dim3(256), 0, s, rb.descs, rb.rc, rb.fixes, rb.cap_fix);
+    hipLaunchKernelGGL(k_fixup, dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.fixes, rb.cap_fix);
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
-    {
-        const WalkArgs wa = {rb.descs, rb.walk, rb.walk_counts, rb.walk_cap, bk};
-        hipLaunchKernelGGL(k_walk, dim3(pb), dim3(256), 0, s, wa);
-    }
+    hipLaunchKernelGGL((k_walk<kWalkItems, kWalkBuf>), dim3(pb), dim3(256), 0, s, rb.descs, rb.walk,
+                       rb.walk_counts, rb.walk_cap, rb.status, cmp_tb, rb.wbuf, rb.wbuf_counts, rb.wbuf_cap);
     H(K_WALK, 1);
 
     H(K_TSCAN, 0);
@@ -1782,16 +1659,13 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_TSCAN, 1);
 
     H(K_COMPACT, 0);
-    {
-        const CompactArgs ca = {rb.descs, rb.nmesh,        rb.status, rb.cpre,   rb.emit,
-                                rb.emit_counts, rb.emit_cap, rb.bcnt,   rb.bucket, rb.bucket_cap};
-        GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
-                        compact_lds_bytes(cmp_tb), s, ca);
-    }
+    GP_LAUNCH_ITEMS(k_compact, cfg.items_compact, dim3(rb.cmp_tiles), dim3(cfg.block_compact),
+                    compact_lds_bytes(cmp_tb), s, rb.descs, rb.nmesh,
+                    rb.status, rb.cpre, rb.emit, rb.emit_counts, rb.emit_cap, rb.wbuf);
     H(K_COMPACT, 1);
 
     H(K_EMIT, 0);
-    hipLaunchKernelGGL(k_emit, dim3(pb), dim3(256), 0, s, rb.descs, rb.emit, rb.emit_counts, rb.emit_cap);
+    hipLaunchKernelGGL(k_emit<4>, dim3(pb), dim3(256), 0, s, rb.descs, rb.emit, rb.emit_counts, rb.emit_cap);
     H(K_EMIT, 1);
     return hipGetLastError();
 }

@@ -200,7 +200,7 @@ namespace {
 // no-allocation entry point plans its single mesh with this directly.
 struct PlanSizes {
     int64_t tri_tiles = 0, he_tiles = 0, cmp_tiles = 0, cap_tips = 0, cap_fix = 0;
-    int64_t walk_cap = 0, emit_cap = 0, bucket_cap = 0;
+    int64_t walk_cap = 0, emit_cap = 0, wbuf_cap = 0;
     size_t out_bytes = 0, tmp_bytes = 0, tmp_mesh = 0;
 };
 
@@ -228,7 +228,7 @@ int plan_core(const gp::LaunchCfg &cfg, const int32_t *nts, const int32_t *nvs, 
         const int64_t nh = 3ll * nt;
         p->out_bytes += 3 * arena_bytes<int32_t>(nh + 1) + arena_bytes<int32_t>(nt + 1) +
                         arena_bytes<int32_t>(nt + 2);
-        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(nt + 4, 4));
+        p->tmp_mesh += 2 * arena_bytes<uint8_t>(align_up(nt + 4, 4)) + arena_bytes<int32_t>(nt + 1);
         total_nt += nt;
         if (p->tri_tiles > 0x7fffffff || p->he_tiles > 0x7fffffff || p->cap_tips > (1ll << 30)) return GP_ERANGE;
     }
@@ -238,19 +238,16 @@ int plan_core(const gp::LaunchCfg &cfg, const int32_t *nts, const int32_t *nvs, 
     const int64_t S = gp::kStripes;
     p->walk_cap = (p->he_tiles + S - 1) / S * th + (2 * p->cap_tips + S - 1) / S + 2;
     p->emit_cap = (p->cmp_tiles + S - 1) / S * tc;
-    // stored loops: kBucketPerTri ints per triangle of each compaction tile
-    // (a header and the half-edges of each loop; the meshes here need about
-    // one per triangle, and loops that find no room are written by k_emit)
-    p->bucket_cap = gp::kBucketPerTri * tc;
-    (void)total_nt;
-    if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff || p->bucket_cap > 0x7fff)
+    // walked loops: at most 3T half-edges in all (each loop is stored once)
+    // plus one rotation index per loop; slack for uneven stripes
+    p->wbuf_cap = align_up((4 * total_nt + S - 1) / S + 4096, 4);
+    if (p->walk_cap * S > 0x7fffffff || p->emit_cap * S > 0x7fffffff || p->wbuf_cap * S > 0x7fffffff)
         return GP_ERANGE;
     p->tmp_bytes = p->tmp_mesh + arena_bytes<gp::MeshDesc>(n) + arena_bytes<gp::RunCounters>(1) +
                    arena_bytes<gp::MeshCounters>(n) + arena_bytes<gp::ListEntry>(p->cap_tips) +
                    arena_bytes<gp::ListEntry>(p->cap_fix) + 2 * arena_bytes<uint64_t>(p->cmp_tiles) +
                    arena_bytes<gp::ListEntry>(p->walk_cap * S) + arena_bytes<gp::EmitEntry>(p->emit_cap * S) +
-                   arena_bytes<int32_t>(p->cmp_tiles) + arena_bytes<int32_t>(p->cmp_tiles * p->bucket_cap) +
-                   2 * arena_bytes<int32_t>(S * gp::kStripePad);
+                   arena_bytes<int32_t>(p->wbuf_cap * S + 32) + 3 * arena_bytes<int32_t>(S * gp::kStripePad);
     return GP_OK;
 }
 
@@ -271,10 +268,10 @@ int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Pla
 }
 
 // Carves the run scratch out of `block` (PlanSizes::tmp_bytes bytes): the
-// run's buffers into *rb, each mesh's label and loop byte arrays into
-// tflag[i], pl[i].  descs holds the planned tile offsets.
+// run's buffers into *rb, each mesh's label, loop and walk-position arrays
+// into tflag[i], pl[i], lpos[i].  descs holds the planned tile offsets.
 void layout_scratch(const PlanSizes &p, const gp::MeshDesc *descs, int n, void *block, gp::RunBuffers *rb,
-                    uint8_t **tflag, uint8_t **pl) {
+                    uint8_t **tflag, uint8_t **pl, int32_t **lpos) {
     const int64_t S = gp::kStripes;
     Arena at{static_cast<char *>(block), p.tmp_bytes, 0};
     *rb = gp::RunBuffers{};
@@ -306,12 +303,13 @@ void layout_scratch(const PlanSizes &p, const gp::MeshDesc *descs, int n, void *
     rb->emit = at.take<gp::EmitEntry>(p.emit_cap * S);
     rb->emit_counts = at.take<int32_t>(S * gp::kStripePad);
     rb->emit_cap = (int32_t)p.emit_cap;
-    rb->bcnt = at.take<int32_t>(p.cmp_tiles);
-    rb->bucket = at.take<int32_t>(p.cmp_tiles * p.bucket_cap);
-    rb->bucket_cap = (int32_t)p.bucket_cap;
+    rb->wbuf = at.take<int32_t>(p.wbuf_cap * S + 32);   // + a 16-byte-group overread at the end
+    rb->wbuf_counts = at.take<int32_t>(S * gp::kStripePad);
+    rb->wbuf_cap = (int32_t)p.wbuf_cap;
     for (int i = 0; i < n; i++) {
         tflag[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));
         pl[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));   // whole words: k_walk claims by OR
+        lpos[i] = at.take<int32_t>(descs[i].nt + 1);
     }
 }
 
@@ -350,6 +348,7 @@ struct GraphEntry {
     void *scratch = nullptr;
     gp::RunBuffers rb{};
     std::vector<uint8_t *> tflag, pl;
+    std::vector<int32_t *> lpos;
     std::vector<gp::MeshDesc> staged;   // the descriptor table last staged into rb.descs
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
@@ -401,7 +400,8 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     const int n = (int)plan.nts.size();
     e.tflag.resize(n);
     e.pl.resize(n);
-    layout_scratch(plan, plan.descs.data(), n, e.scratch, &e.rb, e.tflag.data(), e.pl.data());
+    e.lpos.resize(n);
+    layout_scratch(plan, plan.descs.data(), n, e.scratch, &e.rb, e.tflag.data(), e.pl.data(), e.lpos.data());
     hipGraph_t graph = nullptr;
     hipStream_t s = c->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -854,12 +854,14 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     }
     gp::RunBuffers rb{};
     std::vector<uint8_t *> tflag(n), pl(n);
+    std::vector<int32_t *> lpos(n);
     if (ge) {
         rb = ge->rb;
         tflag = ge->tflag;
         pl = ge->pl;
+        lpos = ge->lpos;
     } else {
-        layout_scratch(plan, plan.descs.data(), n, p_tmp, &rb, tflag.data(), pl.data());
+        layout_scratch(plan, plan.descs.data(), n, p_tmp, &rb, tflag.data(), pl.data(), lpos.data());
     }
     Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
     std::vector<gp_result *> res(n, nullptr);
@@ -897,6 +899,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         d.loop_he = x->loop_he;
         d.tflag = tflag[i];
         d.pl = pl[i];
+        d.lpos = lpos[i];
         d.ctr = rb.ctrs + i;
     }
     hipStream_t s = c->stream;
@@ -976,7 +979,8 @@ int gpolylla_mesh_noalloc(gp_ctx *c, const gp_mesh *m, const gp_result_dev *out,
     DeviceGuard g(c->device);
     gp::RunBuffers rb;
     uint8_t *tflag = nullptr, *pl = nullptr;
-    layout_scratch(plan, &d, 1, base, &rb, &tflag, &pl);
+    int32_t *lpos = nullptr;
+    layout_scratch(plan, &d, 1, base, &rb, &tflag, &pl, &lpos);
     d.xy = m->xy;
     d.org = m->org;
     d.twin = m->twin;
@@ -987,6 +991,7 @@ int gpolylla_mesh_noalloc(gp_ctx *c, const gp_mesh *m, const gp_result_dev *out,
     d.loop_he = out->loop_he;
     d.tflag = tflag;
     d.pl = pl;
+    d.lpos = lpos;
     d.ctr = rb.ctrs;
     hipStream_t s = c->stream;
     // every counter and list the kernels use is cleared by the chain itself

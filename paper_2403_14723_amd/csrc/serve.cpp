@@ -34,22 +34,30 @@ struct Request {
     size_t footprint = 0;   // build bytes; the batch adds its meshing bytes
     Clock::time_point t_submit;
     bool done = false;
+    bool waited = false;   // a gpolylla_serve_wait call holds the ticket
     int status = GP_OK;
     gp_result *result = nullptr;
 };
 
 // Pinned host blocks for results; outlives the server while results hold
-// blocks.
+// blocks.  A request may get a free block of up to twice its size; a block
+// always comes back at its real size.  At most kCap bytes are kept free
+// (blocks beyond that are freed).
 struct PinnedPool {
+    static constexpr size_t kCap = (size_t)4 << 30;
     std::mutex mu;
-    std::multimap<size_t, void *> free_;
-    void *take(size_t n) {
+    std::multimap<size_t, void *> free_;   // by real size
+    size_t bytes = 0;                      // held in free_
+    // A block of at least n bytes; *cap: its real size.
+    void *take(size_t n, size_t *cap) {
         n = align_up(n ? n : kAlign);
         {
             std::lock_guard<std::mutex> lk(mu);
             auto it = free_.lower_bound(n);
             if (it != free_.end() && it->first <= 2 * n) {
                 void *p = it->second;
+                *cap = it->first;
+                bytes -= it->first;
                 free_.erase(it);
                 return p;
             }
@@ -59,11 +67,20 @@ struct PinnedPool {
             (void)hipGetLastError();
             return nullptr;
         }
+        *cap = n;
         return p;
     }
-    void give(void *p, size_t n) {
-        std::lock_guard<std::mutex> lk(mu);
-        free_.emplace(align_up(n ? n : kAlign), p);
+    // Returns block p of real size cap (as take reported it).
+    void give(void *p, size_t cap) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (bytes + cap <= kCap) {
+                bytes += cap;
+                free_.emplace(cap, p);
+                return;
+            }
+        }
+        (void)hipHostFree(p);
     }
     ~PinnedPool() {
         for (auto &kv : free_) (void)hipHostFree(kv.second);
@@ -105,7 +122,7 @@ struct Lane {
     std::vector<gp_mesh *> meshes;
     std::vector<gp_result *> dev;          // device results of the batch
     std::vector<void *> blocks;            // pinned block per request
-    std::vector<size_t> block_bytes;
+    std::vector<size_t> block_bytes;       // its real size
     std::vector<gp_result_info> infos;
     hipEvent_t copied = nullptr;
 };
@@ -198,7 +215,7 @@ void launch(gp_server *s, Lane &L, std::vector<Request *> &batch) {
     L.state = Lane::RUNNING;
 }
 
-// Kernels done: copy every output to a pinned block of exact size.
+// Kernels done: copy every output to a pinned block.
 void start_copies(gp_server *s, Lane &L) {
     const size_t n = L.reqs.size();
     L.blocks.assign(n, nullptr);
@@ -210,8 +227,7 @@ void start_copies(gp_server *s, Lane &L) {
         int rc = gpolylla_result_info(L.dev[i], &info);
         if (rc == GP_OK) {
             const size_t words = 2 * (size_t)info.nh + (size_t)info.npoly + (size_t)info.npoly + 1 + (size_t)info.nloop_he;
-            L.block_bytes[i] = 4 * words;
-            L.blocks[i] = s->pinned->take(L.block_bytes[i]);
+            L.blocks[i] = s->pinned->take(4 * words, &L.block_bytes[i]);
             if (!L.blocks[i]) rc = GP_ENOMEM;
         }
         if (rc == GP_OK) {
@@ -445,10 +461,15 @@ int gpolylla_serve_wait(gp_server *s, uint64_t ticket, int32_t timeout_ms, gp_re
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return GP_EINVAL;
     Request *r = it->second;
+    // one waiter per ticket: the one that returns with the result deletes
+    // the request, so a second waiter is turned away here
+    if (r->waited) return GP_EINVAL;
+    r->waited = true;
     auto pred = [r] { return r->done; };
     if (timeout_ms < 0) {
         s->cv_done.wait(lk, pred);
     } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) {
+        r->waited = false;   // the ticket can be waited for again
         return GP_ETIMEDOUT;
     }
     const int st = r->status;

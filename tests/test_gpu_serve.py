@@ -162,3 +162,32 @@ def test_queue_full_and_wait_timeout(ctx):
         st = srv.stats()
         assert st["rejected"] == again
         assert st["completed"] == 1 + len(accepted) and st["failed"] == 0
+
+
+def test_two_waiters_on_one_ticket(ctx):
+    """Two threads wait for one ticket: one gets the result (equal to the
+    oracle's), the other GP_EINVAL (the ticket is held by the first waiter,
+    or already collected), and neither touches a freed request."""
+    big = W.jittered_grid(1024, seed=13, warp=True)
+    with gp.Server(ctx, pool_bytes=1 << 30, max_batch=1, n_lanes=1) as srv:
+        say("[gpu] serve: two waiters on one ticket")
+        t = srv.submit(big.xy, big.tri)
+        got, errs = [], []
+
+        def waiter():
+            try:
+                got.append(srv.wait(t, 60000))
+            except gp.GPolyllaError as e:
+                errs.append(e.code)
+
+        th = [threading.Thread(target=waiter) for _ in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert len(got) == 1 and errs == [gp.GP_EINVAL]
+        o = oracle.polylla(big.xy, big.tri)
+        g = got[0].copy()
+        got[0].free()
+        for k in KEYS:
+            assert np.array_equal(g[k], getattr(o, k)), k
