@@ -137,7 +137,7 @@ inline size_t compact_lds_bytes(int tile) {
     return sizeof(int) * ((size_t)compact_he_cap(tile) + 2 * (size_t)tile);
 }
 
-enum KernelId { K_INIT = 0, K_LABEL, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
+enum KernelId { K_LABEL = 0, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.

@@ -8,8 +8,8 @@
 //
 // Kernel chain (the eight kernels of the paper's Section 6 / Algorithm 7,
 // regrouped so that every step reads its inputs contiguously):
-//   k_init      clears run counters, per-mesh counters and scan tile status
-//   k_label     longest edge of every triangle (Section 6.1, Algorithm 8)
+//   k_label     longest edge of every triangle (Section 6.1, Algorithm 8);
+//               also clears the run's counters and per-tile totals
 //   k_relink    frontier bits of every half-edge (Section 6.2, Algorithm 9),
 //               the seed bit of terminal edges (Section 6.3, Algorithm 10),
 //               then next/prev of every frontier half-edge by turning around
@@ -33,11 +33,13 @@
 //   bits 2-4  frontier bit of local edges 0..2 (the repair sets more of them)
 //   bit  5    the longest edge is a terminal edge and this triangle holds its
 //             seed half-edge
+//   bit  6    k_walk stored the loop whose minimum lies in this triangle
+//   bit  7    (from k_label to k_relink only) the longest edge is tied
 #include "gp_internal.h"
 
 namespace gp {
 
-const char *const kKernelNames[K_COUNT] = {"k_init", "k_label",     "k_relink",  "k_repair", "k_fixup",
+const char *const kKernelNames[K_COUNT] = {"k_label",     "k_relink",  "k_repair", "k_fixup",
                                            "k_walk", "k_tile_scan", "k_compact", "k_emit"};
 
 constexpr uint32_t kSeedBit = 1u << 5;
@@ -266,38 +268,37 @@ __device__ __forceinline__ void load_to_lds(int *dst, gcint src, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// k_init
-// ---------------------------------------------------------------------------
-
-__global__ void k_init(RunCounters *rc, MeshCounters *ctrs, int nmesh, uint64_t *status, int nstatus,
-                       int32_t *walk_counts, int32_t *emit_counts, int32_t *wbuf_counts) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int stride = gridDim.x * blockDim.x;
-    if (i < kStripes) {
-        walk_counts[i * kStripePad] = 0;
-        emit_counts[i * kStripePad] = 0;
-        wbuf_counts[i * kStripePad] = 0;
-    }
-    if (i == 0) {
-        rc->ntips = 0;
-        rc->unused = 0;
-        rc->nfix = 0;
-        rc->tile_ctr = 0;
-        rc->err = 0;
-    }
-    for (int k = i; k < nmesh; k += stride) {
-        MeshCounters z = {};
-        ctrs[k] = z;
-    }
-    for (int k = i; k < nstatus; k += stride) status[k] = 0ull;
-}
-
-// ---------------------------------------------------------------------------
 // k_label: longest edge of each triangle
 // ---------------------------------------------------------------------------
 
+// What a run clears before its kernels count into it.
+struct ClearArgs {
+    RunCounters *rc;
+    MeshCounters *ctrs;
+    uint64_t *status;   // per compaction tile
+    int nstatus;
+    int32_t *walk_counts, *emit_counts, *wbuf_counts;
+};
+
+// Label byte bit 7: the maximum edge length of the triangle is tied (k_label
+// sets it, k_relink counts it and writes the byte back without it).
+constexpr uint32_t kTieBit = 1u << 7;
+
 template <int ITEMS>
-__global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ descs, int nmesh) {
+__global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ descs, int nmesh, ClearArgs ca) {
+    // the run's counters, list sizes and per-tile totals start at zero for
+    // the kernels that follow (nothing in this kernel counts into them)
+    {
+        const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+        for (int k = gid; k < ca.nstatus; k += stride) ca.status[k] = 0ull;
+        for (int k = gid; k < nmesh; k += stride) ca.ctrs[k] = MeshCounters{};
+        if (gid < kStripes) {
+            ca.walk_counts[gid * kStripePad] = 0;
+            ca.emit_counts[gid * kStripePad] = 0;
+            ca.wbuf_counts[gid * kStripePad] = 0;
+        }
+        if (gid == 0) *ca.rc = RunCounters{};
+    }
     extern __shared__ int4 lds_raw[];
     int *s_org = reinterpret_cast<int *>(lds_raw);
     const int B = blockDim.x, tid = threadIdx.x;
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
                     best = i;
                 }
             }
-            atomicAdd(&d.ctr->nties, 1);
+            best |= (int)kTieBit;   // counted by k_relink
         }
         tflag[t] = (uint8_t)best;
     }
@@ -567,11 +568,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             for (int i = 0; i < 3; i++) s_tw[3 * lt + i] = tw[j][i];
         }
     }
+    int ties = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
         const int t = base + lt;
         const uint32_t L = f[j] & 3u;
+        ties += (lt < cnt && (f[j] & kTieBit)) ? 1 : 0;
         uint32_t out = L;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -587,6 +590,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
         f[j] = lt < cnt ? out : 0u;
         if (lt < cnt) s_f[lt] = (uint8_t)out;
     }
+    if (ties) atomicAdd(&d.ctr->nties, ties);   // (rare)
     __syncthreads();
     // phase 2: next'/prev' of every frontier half-edge.  The next (previous)
     // edge in the triangle is taken when it is frontier itself; otherwise the
@@ -1618,19 +1622,13 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     const int pb = cfg.persistent_blocks, pt = cfg.block_persistent;
     const int cmp_tb = cfg.block_compact * cfg.items_compact;   // triangles per compaction tile
 
-    H(K_INIT, 0);
-    {
-        int n = rb.cmp_tiles > rb.nmesh ? rb.cmp_tiles : rb.nmesh;
-        int grid = (n + 255) / 256;
-        grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
-        hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, s, rb.rc, rb.ctrs, rb.nmesh, rb.status,
-                           rb.cmp_tiles, rb.walk_counts, rb.emit_counts, rb.wbuf_counts);
-    }
-    H(K_INIT, 1);
-
     H(K_LABEL, 0);
-    GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label),
-                    sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh);
+    {
+        const ClearArgs ca = {rb.rc, rb.ctrs, rb.status, rb.cmp_tiles, rb.walk_counts, rb.emit_counts,
+                              rb.wbuf_counts};
+        GP_LAUNCH_ITEMS(k_label, cfg.items_label, dim3(rb.tri_tiles), dim3(cfg.block_label),
+                        sizeof(int) * 3 * (size_t)cfg.block_label * cfg.items_label, s, rb.descs, rb.nmesh, ca);
+    }
     H(K_LABEL, 1);
 
     H(K_RELINK, 0);
