@@ -43,37 +43,64 @@ def algorithmic_bytes(nt, nv, npoly, nloop):
 
 
 def kernel_bytes(name, nt, nv, npoly, nloop):
-    """Algorithmic bytes of one launch of the streaming kernels.
-    The list-driven kernels (k_repair, k_fixup, k_walk, k_emit) touch only the
-    few loops and vertices on their lists and are not roofline candidates."""
+    """Each streaming kernel's share of the algorithmic bytes (the terms of
+    48T + 8V + 8P + 4Fh + 4 that it reads or writes; label bytes and other
+    intermediate state are not counted).  The shares add up to the whole
+    path's bytes.  The list-driven kernels (k_repair, k_fixup, k_walk,
+    k_emit) and the tile scan move only intermediate state: no share."""
     return {
-        "k_label": 12 * nt + 8 * nv + nt,                     # org, xy -> tflag
-        "k_relink": 12 * nt + nt + 24 * nt + 2 * nt,          # twin, tflag -> next, prev, tflag, pl
-        "k_compact": 2 * nt + 8 * npoly + 4 * nloop,          # pl, tflag -> seeds, loop_off, loop_he
+        "k_label": 12 * nt + 8 * nv,             # org, xy in
+        "k_relink": 36 * nt,                     # twin in; next', prev' out
+        "k_compact": 8 * npoly + 4 * nloop + 4,  # seeds, loop_off, loop_he out
     }.get(name)
 
 
-def measured_traffic(kernel, workload="plain_4096x4096_warped"):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of
-    `workload` (FETCH_SIZE + WRITE_SIZE, calibrated), when the summary was
-    taken on the kernel sources as they are now; else None."""
+KERNEL_BYTES_FORMULA = {"k_label": "12T + 8V (org, xy in)", "k_relink": "36T (twin in; next', prev' out)",
+                        "k_compact": "8P + 4Fh + 4 (seeds, loop_off, loop_he out)"}
+
+
+def profile_record(workload):
+    """The traffic record of the committed rocprofv3 summary of `workload`
+    (per-launch HBM bytes of every kernel of the chain, calibrated
+    FETCH_SIZE + WRITE_SIZE, and rocprofv3's average durations), when the
+    summary was taken on the kernel sources as they are now; else (None,
+    None)."""
     from paper_2403_14723_amd import prof
     here = os.path.dirname(os.path.abspath(__file__))
     sha = prof.sources_sha256()
     for path in sorted(glob.glob(os.path.join(here, "profiles", f"*_{workload}.md"))):
         with open(path) as f:
             rec = prof.traffic_line(f.read())
-        if rec and rec.get("kernel") == kernel and rec.get("sources_sha256") == sha:
-            return rec["fetch_bytes"] + rec["write_bytes"], os.path.basename(path)
+        if rec and rec.get("sources_sha256") == sha:
+            return rec, os.path.basename(path)
     return None, None
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mesh):
-    """The oracle, single-threaded, on the whole workload (one run)."""
+    """The oracle, single-threaded, on the whole workload (one run), built
+    for this host (-O3 -march=native) and pinned to one core."""
     import oracle
-    t0 = time.perf_counter()
-    res = oracle.polylla(mesh.xy, mesh.tri)
-    wall = time.perf_counter() - t0
+    oracle.use_library(oracle.build_native_library())
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        res = oracle.polylla(mesh.xy, mesh.tri)
+        wall = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
     st = res.stats
     mesh_ms = st["ms_label"] + st["ms_repair"] + st["ms_traverse"] + st["ms_canon"]
     return {
@@ -85,6 +112,11 @@ def cpu_baseline(mesh):
                   f"meshing phases only (label+repair+traversal+canonical order, {mesh_ms:.0f} ms); "
                   f"the half-edge build took {st['ms_build']:.0f} ms more; wall {wall:.1f} s",
         "build_plus_mesh_mtri_s": round(mesh.nt / ((mesh_ms + st["ms_build"]) * 1e-3) / 1e6, 3),
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+        "cores_allowed": len(allowed),
+        "core": core,
+        "compiler": "gcc -O3 -march=native (built on this host at run time)",
     }, res
 
 
@@ -103,6 +135,13 @@ def bench_batched(gp, W, stream, steps):
     hs = [ctx.build_halfedges(m.xy, m.tri) for m in meshes]
     T = sum(m.nt for m in meshes)
     flags = gp.GP_ASYNC | gp.GP_GRAPH
+    # the batch's algorithmic bytes: the sum over its meshes
+    b_alg = 0
+    for h, m in zip(hs, meshes):
+        r = ctx.mesh(h)
+        i = r.info()
+        r.free()
+        b_alg += algorithmic_bytes(m.nt, m.nv, i["npoly"], i["nloop_he"])
 
     def run_batched():
         for r in ctx.mesh_batch(hs, flags):
@@ -134,6 +173,10 @@ def bench_batched(gp, W, stream, steps):
         out[f"{name}_wall_ms"] = round(wall, 4)
         out[f"{name}_mtri_s"] = round(T / (max(ms, wall) * 1e-3) / 1e6, 1)
     out["batched_over_plain"] = round(out["batched_mtri_s"] / out["plain_mtri_s"], 2)
+    bms = max(out["batched_ms"], out["batched_wall_ms"])
+    out["roofline"] = {"alg_bytes": b_alg, "alg_bytes_formula": "sum over the meshes of 48T + 8V + 8P + 4Fh + 4",
+                       "achieved_GBs": round(b_alg / (bms * 1e-3) / 1e9, 1), "peak_GBs": HBM_PEAK_GBS,
+                       "frac": round(b_alg / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     for h in hs:
         h.free()
     ctx.close()
@@ -446,10 +489,18 @@ def main():
             kernels[name]["alg_GBs"] = round(kb / (avg * 1e-3) / 1e9, 1)
     dom = max((k for k in kms if kernel_bytes(k, nt, nv, P, Fh)), key=lambda k: kms[k][0])
     dom_ms = kms[dom][0]
+    dom_launches = kms[dom][1]
     dom_bytes = kernel_bytes(dom, nt, nv, P, Fh)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     value = nt / (ms_per_step * 1e-3) / 1e6
-    traffic, traffic_src = measured_traffic(dom.split("<")[0], mesh.name)
+    rec, rec_src = profile_record(mesh.name)
+    chain_rec = (rec or {}).get("chain", {})
+    dom_rec = chain_rec.get(dom.split("<")[0])
+    traffic = dom_rec["fetch_bytes"] + dom_rec["write_bytes"] if dom_rec else None
+    chain_traffic = None
+    if chain_rec and all(k.split("<")[0] in chain_rec for k in kms):
+        chain_traffic = sum(chain_rec[k.split("<")[0]]["fetch_bytes"] + chain_rec[k.split("<")[0]]["write_bytes"]
+                            for k in kms)
 
     batched = served = delaunay = transfers = band = None
     if not args.no_forms:
@@ -492,9 +543,20 @@ def main():
                    "ties": info["nties"], "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_source": traffic_src, "alg_bytes_per_launch": dom_bytes},
-        "whole_path": {"alg_bytes": b_alg, "alg_GBs": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
-                       "frac": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": dom_bytes,
+                     "alg_bytes_formula": KERNEL_BYTES_FORMULA[dom.split("<")[0]],
+                     "avg_ms": round(dom_ms, 5),
+                     "timing": f"HIP events around each kernel on the bench stream, profiled pass, "
+                               f"average of {dom_launches} launches",
+                     "rocprof_avg_ms": round(dom_rec["avg_us"] / 1e3, 5) if dom_rec and dom_rec.get("avg_us") else None,
+                     "profile": rec_src},
+        "whole_path": {"alg_bytes": b_alg, "alg_bytes_formula": "48T + 8V + 8P + 4Fh + 4",
+                       "alg_GBs": round(b_alg / (ms_per_step * 1e-3) / 1e9, 1),
+                       "frac": round(b_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "timing": "HIP events around the timed graph replays (ms_per_step)",
+                       "measured_traffic": chain_traffic,
+                       "traffic_over_alg": round(chain_traffic / b_alg, 3) if chain_traffic else None},
         "kernels": kernels,
         "separate": {"h2d_ms": round(h2d_ms, 3), "build_ms": round(build_ms, 3), "d2h_ms": round(d2h_ms, 3),
                      "with_copies_mtri_s": round(nt / ((h2d_ms + build_ms + ms_per_step + d2h_ms) * 1e-3) / 1e6, 2)},

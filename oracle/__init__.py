@@ -43,15 +43,38 @@ def build_library(force: bool = True) -> str:
     return _LIB
 
 
+_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build_native_library() -> str:
+    """Compiles liboracle_native.so for the host it runs on (-O3
+    -march=native): the CPU baseline's build, made on the machine that times
+    it.  The tests use the portable build."""
+    tmp = _NATIVE + f".{os.getpid()}.tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _NATIVE)
+    return _NATIVE
+
+
 _lib = None
+_lib_path = None
+
+
+def use_library(path: str) -> None:
+    """Makes every later oracle call in this process use the library at path
+    (built from the same source)."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _lib_path or _LIB
+        if path == _LIB and not os.path.exists(_LIB):
             build_library()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         p32 = ctypes.POINTER(ctypes.c_int32)
         p8 = ctypes.POINTER(ctypes.c_uint8)
         lib.orc_polylla.argtypes = [p32, ctypes.c_int32, p32, ctypes.c_int32,

@@ -9,9 +9,10 @@ Counter scale: rocprofv3 reports FETCH_SIZE and WRITE_SIZE in KiB per dispatch,
 and on this device FETCH_SIZE counts half of the bytes a plain copy kernel
 reads.  Both are calibrated on the largest copy kernel of the profiled run,
 which moves 12*T bytes (the size of the triangle array and of each of next'
-and prev'), and the calibrated bytes per launch are written into the summary
-with a hash of the kernel sources, so bench.py can tell whether the counters
-still describe the kernels it runs.
+and prev'), and the calibrated bytes per launch of every kernel of the
+meshing chain (and their rocprofv3 average durations) are written into the
+summary with a hash of the kernel sources, so bench.py can tell whether the
+counters still describe the kernels it runs.
 """
 from __future__ import annotations
 
@@ -27,6 +28,8 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/mesh_kernels.hip", "csrc/gp_internal.h")
 MARK = "<!-- traffic:"
+# the meshing chain's kernels, in launch order
+CHAIN = ("k_label", "k_relink", "k_repair", "k_fixup", "k_walk", "k_tile_scan", "k_compact", "k_emit")
 
 
 def sources_sha256() -> str:
@@ -101,6 +104,8 @@ def main():
               f"written): FETCH_SIZE x {f_scale:.3f}, WRITE_SIZE x {w_scale:.3f} (KiB -> bytes).", "",
               "| kernel | dispatches | fetch MB | write MB |", "|---|---|---|---|"]
     rec = None
+    avg_us = {name.split("<")[0]: avg for name, _, avg, _ in read_stats(a.stats)}
+    chain = {}
     for k in sorted(set(fetch) | set(write)):
         fv, wv = fetch[k].get("FETCH_SIZE", []), write[k].get("WRITE_SIZE", [])
         if not fv or not wv:
@@ -108,10 +113,16 @@ def main():
         fb = sum(fv) / len(fv) * 1024 * f_scale
         wb = sum(wv) / len(wv) * 1024 * w_scale
         lines.append(f"| {k} | {len(fv)} | {fb / 1e6:.1f} | {wb / 1e6:.1f} |")
-        if short(k).split("<")[0] == a.kernel:
+        base = short(k).split("<")[0]
+        if base in CHAIN:
+            chain[base] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "avg_us": avg_us.get(base)}
+        if base == a.kernel:
             rec = {"kernel": a.kernel, "fetch_bytes": round(fb), "write_bytes": round(wb),
-                   "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+                   "avg_us": avg_us.get(base), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
                    "sources_sha256": sources_sha256()}
+    if rec:
+        rec["triangles"] = a.triangles
+        rec["chain"] = chain
     for d in a.pmc:
         acc = read_counters(d)
         names = sorted({c for k in acc for c in acc[k]})
