@@ -241,6 +241,65 @@ def bench_transfers(gp, W, stream, reps=5):
     return out
 
 
+def _pipelined(gp, ctx, meshes, group, loops_only, reps=2):
+    """Host-to-host rate of gpolylla_mesh_jobs over `meshes` (one job each):
+    inputs in pinned host memory (one buffer per distinct mesh), outputs into
+    one pinned set of buffers of the largest job's size that every job
+    overwrites in turn (the downloads of one call run one after another on one
+    stream).  Best of reps timed calls after an untimed one."""
+    import torch
+    distinct = {id(m): m for m in meshes}
+    pin = {k: (torch.from_numpy(m.xy.reshape(-1)).pin_memory(), torch.from_numpy(m.tri.reshape(-1)).pin_memory())
+           for k, m in distinct.items()}
+    tmax = max(m.nt for m in meshes)
+    out = {k: torch.empty(max(n, 1), dtype=torch.int32).pin_memory()
+           for k, n in (("next", 3 * tmax), ("prev", 3 * tmax), ("seeds", tmax), ("loop_off", tmax + 1),
+                        ("loop_he", 3 * tmax))}
+    arr = (gp.gp_job * len(meshes))()
+    for j, m in zip(arr, meshes):
+        xy, tri = pin[id(m)]
+        j.xy, j.nv, j.tri, j.nt = xy.data_ptr(), m.nv, tri.data_ptr(), m.nt
+        for k in ("next", "prev"):
+            setattr(j, k, None if loops_only else out[k].data_ptr())
+        for k in ("seeds", "loop_off", "loop_he"):
+            setattr(j, k, out[k].data_ptr())
+    best = None
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = gp.gpolylla_mesh_jobs(ctx.handle, arr, group)
+        dt = time.perf_counter() - t0
+        assert rc == gp.GP_OK, (rc, [j.status for j in arr if j.status])
+        if rep and (best is None or dt < best):
+            best = dt
+    T = sum(m.nt for m in meshes)
+    return round(T / best / 1e6, 1), round(best * 1e3, 3)
+
+
+def bench_pipeline(gp, W, stream, big):
+    """With-copies rates from host memory to host memory, through the
+    overlapped job pipeline (gpolylla_mesh_jobs), for the plain
+    configurations (a list of copies of one mesh) and the 512-mesh batch:
+    with every output copied back and with the loops only (seeds, loop_off,
+    loop_he: next'/prev' follow from them)."""
+    ctx = gp.Context(0, stream=stream.cuda_stream)
+    cases = [("plain_32x32", [W.plain_small()] * 2048, 512 * 2048),
+             ("plain_1024x1024", [W.plain_scale()] * 16, 2 * 2097152),
+             (big.name, [big] * 6, big.nt)]
+    batch = W.batch_meshes(512, seed=3)
+    cases.append(("batch512_s3", batch, sum(m.nt for m in batch) // 8 + 1))
+    out = {}
+    for name, meshes, group in cases:
+        full, full_ms = _pipelined(gp, ctx, meshes, group, False)
+        loops, loops_ms = _pipelined(gp, ctx, meshes, group, True)
+        out[name] = {"jobs": len(meshes), "triangles": sum(m.nt for m in meshes), "group_triangles": group,
+                     "with_copies_mtri_s": full, "ms": full_ms,
+                     "loops_only_with_copies_mtri_s": loops, "loops_only_ms": loops_ms}
+        log(f"[bench] pipeline {name}: {out[name]}")
+    ctx.close()
+    return out
+
+
 def _graph_form(gp, stream, m, steps):
     """Graph-replay time of the meshing chain on mesh m (inputs resident),
     its counts, and per-kernel times from a profiled pass."""
@@ -502,7 +561,7 @@ def main():
         chain_traffic = sum(chain_rec[k.split("<")[0]]["fetch_bytes"] + chain_rec[k.split("<")[0]]["write_bytes"]
                             for k in kms)
 
-    batched = served = delaunay = transfers = band = None
+    batched = served = delaunay = transfers = band = pipeline = None
     if not args.no_forms:
         log("[bench] one row band of an 8-way split (two halo rows)")
         band = bench_band(gp, W, stream, mesh, max(5, args.steps // 2))
@@ -510,6 +569,8 @@ def main():
         log("[bench] transfers of the smaller plain configurations")
         transfers = bench_transfers(gp, W, stream)
         log(f"[bench] {transfers}")
+        log("[bench] overlapped host-to-host pipeline")
+        pipeline = bench_pipeline(gp, W, stream, mesh)
         log("[bench] general-position workload (Delaunay, 1M points)")
         delaunay = bench_delaunay(gp, W, stream, max(5, args.steps // 2))
         log(f"[bench] {delaunay}")
@@ -565,6 +626,7 @@ def main():
         "delaunay": delaunay,
         "band": band,
         "transfers": transfers,
+        "pipeline": pipeline,
         "cpu_baseline": cpu,
     }
     if cpu:

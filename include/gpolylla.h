@@ -199,6 +199,51 @@ void gpolylla_result_free(gp_result *res);
 /* Waits until all queued work of the context has finished. */
 int gpolylla_ctx_sync(gp_ctx *ctx);
 
+/* ---- host-to-host jobs with overlapped copies ---------------------------- */
+
+/*
+ * The paper measures the copies to and from the device beside the kernels
+ * (Section 7, the copy columns of Table 1) and finds that they take most of
+ * the time of a run (Section 8).  gpolylla_mesh_jobs takes triangulations in
+ * host memory and returns their polygons in host memory, overlapping the
+ * copies of one group of jobs with the copies, builds and meshing of the
+ * next: in a long enough list the time per job approaches that of its slower
+ * copy direction, not the sum of all steps.
+ *
+ * One job: inputs as for gpolylla_build_halfedges (host xy: 2*nv int32, tri:
+ * 3*nt int32); outputs into caller-allocated host buffers of capacity
+ * next, prev: 3*nt (both NULL: only the loops are copied back);
+ * seeds: nt; loop_off: nt + 1; loop_he: 3*nt.  npoly and nloop_he receive
+ * the counts (the filled lengths are npoly, npoly + 1 and nloop_he), status
+ * the job's own result (a build error, GP_ECORRUPT, ...).  The buffers must
+ * stay valid until the call returns; pinned host memory (hipHostMalloc) is
+ * needed for the copies to overlap (pageable memory works, serialised).
+ */
+typedef struct {
+    const int32_t *xy;
+    int32_t nv;
+    const int32_t *tri;
+    int32_t nt;
+    int32_t *next, *prev;
+    int32_t *seeds, *loop_off, *loop_he;
+    int32_t npoly, nloop_he;   /* out */
+    int32_t status;            /* out */
+    int32_t reserved;
+} gp_job;
+
+/*
+ * Meshes jobs[0..n) in order.  Consecutive jobs are grouped up to
+ * group_triangles triangles (0: 8M; a larger job is a group of its own) and
+ * each group is one batched run (gpolylla_mesh_batch); flags: 0 or GP_GRAPH.
+ * Uses the context's stream for uploads, builds and runs, and a stream of its
+ * own for the downloads; returns when every job's outputs are in host memory.
+ * Returns GP_OK when every job succeeded, else the first failed job's status
+ * (every job's own status is set either way); GP_EINVAL for a null or
+ * inconsistent argument (nothing run).  Not to be called concurrently with
+ * other calls on the same context.
+ */
+int gpolylla_mesh_jobs(gp_ctx *ctx, gp_job *jobs, int32_t n, int64_t group_triangles, uint32_t flags);
+
 /* ---- meshing without allocation ----------------------------------------- */
 
 /* Counts of one gpolylla_mesh_noalloc run, written by the device when the run

@@ -69,6 +69,14 @@ class gp_dev_counts(ctypes.Structure):
 GP_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
+class gp_job(ctypes.Structure):
+    _fields_ = [("xy", ctypes.c_void_p), ("nv", ctypes.c_int32), ("tri", ctypes.c_void_p), ("nt", ctypes.c_int32),
+                ("next", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("seeds", ctypes.c_void_p),
+                ("loop_off", ctypes.c_void_p), ("loop_he", ctypes.c_void_p),
+                ("npoly", ctypes.c_int32), ("nloop_he", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -115,6 +123,8 @@ def _load():
         "gpolylla_result_device": (ctypes.c_int, [_P, ctypes.POINTER(gp_result_dev)]),
         "gpolylla_result_free": (None, [_P]),
         "gpolylla_mesh_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(gp_result_dev), _P]),
+        "gpolylla_mesh_jobs": (ctypes.c_int, [_P, ctypes.POINTER(gp_job), ctypes.c_int32, ctypes.c_int64,
+                                              ctypes.c_uint32]),
         "gpolylla_serve_start": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_opts), ctypes.POINTER(_P)]),
         "gpolylla_serve_submit": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_uint64)]),
@@ -145,7 +155,8 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_ctx_set_launch", "gpolylla_ctx_get_launch",
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
-            "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_serve_start", "gpolylla_serve_submit",
+            "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_mesh_jobs",
+            "gpolylla_serve_start", "gpolylla_serve_submit",
             "gpolylla_serve_wait", "gpolylla_serve_stats", "gpolylla_serve_reset_stats", "gpolylla_serve_stop"]
 
 
@@ -308,6 +319,12 @@ def gpolylla_mesh_noalloc(ctx, mesh, out: gp_result_dev, counts_ptr: int) -> int
     """Queues a meshing run into caller-allocated device buffers (out, and
     counts_ptr: device memory for a gp_dev_counts); returns the C status."""
     return _load().gpolylla_mesh_noalloc(ctx, mesh, ctypes.byref(out), ctypes.c_void_p(counts_ptr))
+
+
+def gpolylla_mesh_jobs(ctx, jobs, group_triangles: int = 0, flags: int = 0) -> int:
+    """Runs a ctypes array of gp_job (pointers filled in by the caller);
+    returns the C status (every job's own status is in jobs[i].status)."""
+    return _load().gpolylla_mesh_jobs(ctx, jobs, len(jobs), group_triangles, flags)
 
 
 def gpolylla_serve_start(ctx, opts: gp_serve_opts | None = None):

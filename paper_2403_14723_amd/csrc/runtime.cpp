@@ -317,6 +317,158 @@ void layout_scratch(const PlanSizes &p, const gp::MeshDesc *descs, int n, void *
 
 namespace gprt {
 
+namespace {
+
+// One half-edge build, in three stages around the two checks of its inputs
+// (orientation and indices first, then the twin matching), so that many
+// builds can share each host check.
+struct BuildJob {
+    gp_mesh *m = nullptr;
+    void *p_tmp = nullptr;
+    gp::BuildBuffers b{};
+    unsigned long long *key_h = nullptr;   // pinned: the error key after a stage
+    int32_t *nflip_h = nullptr;            // pinned: triangles flipped to CCW
+    int rc = GP_OK;
+};
+
+void build_abort(gp_ctx *c, BuildJob &j) {
+    if (j.p_tmp) c->pool.release(j.p_tmp);
+    j.p_tmp = nullptr;
+    if (j.m) gpolylla_mesh_free(j.m);
+    j.m = nullptr;
+}
+
+// Stage 0: allocation, input copies, clears and the orientation kernels
+// (which also check every index and coordinate), all queued.
+int build_stage0(gp_ctx *c, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt, uint32_t flags,
+                 BuildJob &j) {
+    if (nv < 0 || nt < 0) return GP_EINVAL;
+    if ((nv > 0 && !xy) || (nt > 0 && !tri)) return GP_EINVAL;
+    if (3ll * nt >= (1ll << 31)) return GP_ERANGE;
+    const bool in_dev = (flags & GP_IN_DEVICE) != 0;
+    const int64_t nh = 3ll * nt;
+    gp_mesh *m = new (std::nothrow) gp_mesh();
+    if (!m) return GP_ENOMEM;
+    m->ctx = c;
+    m->nv = nv;
+    m->nt = nt;
+    j.m = m;
+    void *p_xy = nullptr, *p_org = nullptr, *p_twin = nullptr;
+    int rc = c->pool.alloc(sizeof(int2) * (size_t)std::max<int64_t>(nv, 1), &p_xy);
+    m->xy = static_cast<int2 *>(p_xy);
+    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1), &p_org);
+    m->org = static_cast<int32_t *>(p_org);
+    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1), &p_twin);
+    m->twin = static_cast<int32_t *>(p_twin);
+    const int32_t scan_tiles = gp::build_scan_tiles(nv);
+    const size_t tmp_bytes = arena_bytes<int32_t>(nv + 1) * 2 + arena_bytes<int32_t>(nv + 1) +
+                             arena_bytes<int2>(nh + 1) + arena_bytes<uint64_t>(scan_tiles) +
+                             arena_bytes<int32_t>(4) + arena_bytes<unsigned long long>(1) +
+                             (in_dev ? 0 : arena_bytes<int32_t>(nh + 1));
+    if (rc == GP_OK) rc = c->pool.alloc(tmp_bytes, &j.p_tmp);
+    if (rc != GP_OK) return rc;
+    Arena a{static_cast<char *>(j.p_tmp), tmp_bytes, 0};
+    gp::BuildBuffers &b = j.b;
+    b.nv = nv;
+    b.nt = nt;
+    b.org = m->org;
+    b.twin = m->twin;
+    b.deg = a.take<int32_t>(nv + 1);
+    b.fill = a.take<int32_t>(nv + 1);
+    b.vstart = a.take<int32_t>(nv + 1);
+    b.bucket = a.take<int2>(nh + 1);
+    b.scan_status = a.take<uint64_t>(scan_tiles);
+    int32_t *small = a.take<int32_t>(4);
+    b.scan_ctr = small;
+    b.nflipped = small + 1;
+    b.err_key = a.take<unsigned long long>(1);
+    int32_t *tri_dev = in_dev ? const_cast<int32_t *>(tri) : a.take<int32_t>(nh + 1);
+    b.xy = m->xy;
+    b.tri = tri_dev;
+    hipStream_t s = c->stream;
+    const hipMemcpyKind kind = in_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((nv > 0 && hipMemcpyAsync(m->xy, xy, sizeof(int2) * (size_t)nv, kind, s) != hipSuccess) ||
+        (!in_dev && nt > 0 &&
+         hipMemcpyAsync(tri_dev, tri, sizeof(int32_t) * (size_t)nh, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemsetAsync(b.deg, 0, sizeof(int32_t) * (size_t)(nv + 1), s) != hipSuccess ||
+        hipMemsetAsync(b.fill, 0, sizeof(int32_t) * (size_t)(nv + 1), s) != hipSuccess ||
+        hipMemsetAsync(b.scan_status, 0, sizeof(uint64_t) * (size_t)scan_tiles, s) != hipSuccess ||
+        hipMemsetAsync(small, 0, sizeof(int32_t) * 4, s) != hipSuccess ||
+        hipMemsetAsync(b.err_key, 0xff, sizeof(unsigned long long), s) != hipSuccess ||
+        gp::launch_build_orient(b, s) != hipSuccess ||
+        hipMemcpyAsync(j.key_h, b.err_key, sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GP_EHIP;
+    }
+    return GP_OK;
+}
+
+// Stage 1 (after the stream has drained stage 0): the inputs passed their
+// checks; queue the twin matching and the readbacks of its checks.
+int build_stage1(gp_ctx *c, BuildJob &j) {
+    if (*j.key_h != ~0ull) return -(int)(*j.key_h & 0xff);
+    hipStream_t s = c->stream;
+    if (gp::launch_build_link(j.b, s) != hipSuccess ||
+        hipMemcpyAsync(j.key_h, j.b.err_key, sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(j.nflip_h, j.b.nflipped, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GP_EHIP;
+    }
+    return GP_OK;
+}
+
+// Stage 2 (after the stream has drained stage 1): the mesh is complete.
+int build_stage2(gp_ctx *c, BuildJob &j) {
+    if (*j.key_h != ~0ull) return -(int)(*j.key_h & 0xff);
+    j.m->nflipped = *j.nflip_h;
+    c->pool.release(j.p_tmp);
+    j.p_tmp = nullptr;
+    return GP_OK;
+}
+
+}  // namespace
+
+int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
+               const int32_t *nt, uint32_t flags, gp_mesh **out, int *status) {
+    std::vector<BuildJob> jobs(n);
+    const size_t hb = 16 * (size_t)std::max(n, 1);
+    char *host = static_cast<char *>(pinned_take(c, hb));
+    if (!host) return GP_ENOMEM;
+    for (int i = 0; i < n; i++) {
+        jobs[i].key_h = reinterpret_cast<unsigned long long *>(host + 16 * i);
+        jobs[i].nflip_h = reinterpret_cast<int32_t *>(host + 16 * i + 8);
+        out[i] = nullptr;
+    }
+    auto drain = [&]() {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            for (BuildJob &j : jobs)
+                if (j.rc == GP_OK) j.rc = GP_EHIP;
+        }
+    };
+    for (int i = 0; i < n; i++) jobs[i].rc = build_stage0(c, xy[i], nv[i], tri[i], nt[i], flags, jobs[i]);
+    drain();
+    for (BuildJob &j : jobs)
+        if (j.rc == GP_OK) j.rc = build_stage1(c, j);
+    drain();
+    for (BuildJob &j : jobs)
+        if (j.rc == GP_OK) j.rc = build_stage2(c, j);
+    // a failed job's memory goes back after the stream has drained its work
+    bool failed = false;
+    for (BuildJob &j : jobs) failed |= j.rc != GP_OK;
+    if (failed) drain();
+    for (int i = 0; i < n; i++) {
+        status[i] = jobs[i].rc;
+        if (jobs[i].rc == GP_OK) {
+            out[i] = jobs[i].m;
+        } else {
+            build_abort(c, jobs[i]);
+        }
+    }
+    pinned_give(c, host, hb);
+    return GP_OK;
+}
+
 size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device) {
     const int64_t nh = 3 * nt;
     const size_t keep = align_up(sizeof(int2) * (size_t)std::max<int64_t>(nv, 1)) +
@@ -681,93 +833,12 @@ int gpolylla_build_halfedges(gp_ctx *c, const int32_t *xy, int32_t nv, const int
                              uint32_t flags, gp_mesh **out) {
     if (!c || !out) return GP_EINVAL;
     *out = nullptr;
-    if (nv < 0 || nt < 0) return GP_EINVAL;
-    if ((nv > 0 && !xy) || (nt > 0 && !tri)) return GP_EINVAL;
-    if (3ll * nt >= (1ll << 31)) return GP_ERANGE;
     DeviceGuard g(c->device);
-    const bool in_dev = (flags & GP_IN_DEVICE) != 0;
-    const int64_t nh = 3ll * nt;
-
-    gp_mesh *m = new (std::nothrow) gp_mesh();
-    if (!m) return GP_ENOMEM;
-    m->ctx = c;
-    m->nv = nv;
-    m->nt = nt;
-    int rc = GP_OK;
-    void *p_xy = nullptr, *p_org = nullptr, *p_twin = nullptr, *p_tmp = nullptr;
-    rc = c->pool.alloc(sizeof(int2) * (size_t)std::max<int64_t>(nv, 1), &p_xy);
-    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1), &p_org);
-    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nh, 1), &p_twin);
-    const int32_t scan_tiles = gp::build_scan_tiles(nv);
-    const size_t tmp_bytes = arena_bytes<int32_t>(nv + 1) * 2 + arena_bytes<int32_t>(nv + 1) +
-                             arena_bytes<int2>(nh + 1) + arena_bytes<uint64_t>(scan_tiles) +
-                             arena_bytes<int32_t>(4) + arena_bytes<unsigned long long>(1) +
-                             (in_dev ? 0 : arena_bytes<int32_t>(nh + 1));
-    if (rc == GP_OK) rc = c->pool.alloc(tmp_bytes, &p_tmp);
-    if (rc != GP_OK) {
-        c->pool.release(p_xy);
-        c->pool.release(p_org);
-        c->pool.release(p_twin);
-        c->pool.release(p_tmp);
-        delete m;
-        return rc;
-    }
-    m->xy = static_cast<int2 *>(p_xy);
-    m->org = static_cast<int32_t *>(p_org);
-    m->twin = static_cast<int32_t *>(p_twin);
-    Arena a{static_cast<char *>(p_tmp), tmp_bytes, 0};
-    gp::BuildBuffers b{};
-    b.nv = nv;
-    b.nt = nt;
-    b.org = m->org;
-    b.twin = m->twin;
-    b.deg = a.take<int32_t>(nv + 1);
-    b.fill = a.take<int32_t>(nv + 1);
-    b.vstart = a.take<int32_t>(nv + 1);
-    b.bucket = a.take<int2>(nh + 1);
-    b.scan_status = a.take<uint64_t>(scan_tiles);
-    int32_t *small = a.take<int32_t>(4);
-    b.scan_ctr = small;
-    b.nflipped = small + 1;
-    b.err_key = a.take<unsigned long long>(1);
-    int32_t *tri_dev = in_dev ? const_cast<int32_t *>(tri) : a.take<int32_t>(nh + 1);
-    b.xy = m->xy;
-    b.tri = tri_dev;
-
-    auto fail = [&](int code) {
-        (void)hipStreamSynchronize(c->stream);
-        c->pool.release(p_tmp);
-        gpolylla_mesh_free(m);
-        return code;
-    };
-    hipStream_t s = c->stream;
-    const hipMemcpyKind kind = in_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (nv > 0 && hipMemcpyAsync(m->xy, xy, sizeof(int2) * (size_t)nv, kind, s) != hipSuccess)
-        return (void)hipGetLastError(), fail(GP_EHIP);
-    if (!in_dev && nt > 0 &&
-        hipMemcpyAsync(tri_dev, tri, sizeof(int32_t) * (size_t)nh, hipMemcpyHostToDevice, s) != hipSuccess)
-        return (void)hipGetLastError(), fail(GP_EHIP);
-    if (hipMemsetAsync(b.deg, 0, sizeof(int32_t) * (size_t)(nv + 1), s) != hipSuccess ||
-        hipMemsetAsync(b.fill, 0, sizeof(int32_t) * (size_t)(nv + 1), s) != hipSuccess ||
-        hipMemsetAsync(b.scan_status, 0, sizeof(uint64_t) * (size_t)scan_tiles, s) != hipSuccess ||
-        hipMemsetAsync(small, 0, sizeof(int32_t) * 4, s) != hipSuccess ||
-        hipMemsetAsync(b.err_key, 0xff, sizeof(unsigned long long), s) != hipSuccess)
-        return (void)hipGetLastError(), fail(GP_EHIP);
-    if (gp::launch_build_orient(b, s) != hipSuccess) return (void)hipGetLastError(), fail(GP_EHIP);
-    unsigned long long key = ~0ull;
-    if (hipMemcpyAsync(&key, b.err_key, sizeof(key), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return (void)hipGetLastError(), fail(GP_EHIP);
-    if (key != ~0ull) return fail(-(int)(key & 0xff));
-    if (gp::launch_build_link(b, s) != hipSuccess) return (void)hipGetLastError(), fail(GP_EHIP);
-    int32_t nflip = 0;
-    if (hipMemcpyAsync(&key, b.err_key, sizeof(key), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&nflip, b.nflipped, sizeof(nflip), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return (void)hipGetLastError(), fail(GP_EHIP);
-    if (key != ~0ull) return fail(-(int)(key & 0xff));
-    m->nflipped = nflip;
-    c->pool.release(p_tmp);
+    gp_mesh *m = nullptr;
+    int st = GP_OK;
+    const int rc = gprt::build_many(c, 1, &xy, &nv, &tri, &nt, flags, &m, &st);
+    if (rc != GP_OK) return rc;
+    if (st != GP_OK) return st;
     *out = m;
     return GP_OK;
 }

@@ -151,6 +151,13 @@ struct DeviceGuard {
     }
 };
 
+// Builds n half-edge structures (the work of gpolylla_build_halfedges for
+// each) with two host checks in all, on the context's stream: out[i] and
+// status[i] per build.  Returns GP_ENOMEM when the host staging cannot be
+// allocated (nothing built), else GP_OK.
+int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
+               const int32_t *nt, uint32_t flags, gp_mesh **out, int *status);
+
 // device bytes gpolylla_build_halfedges takes from the pool
 size_t build_footprint(int64_t nv, int64_t nt, bool inputs_on_device);
 // device bytes gpolylla_mesh_batch takes from the pool for meshes of these sizes
