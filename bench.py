@@ -360,9 +360,10 @@ def bench_band(gp, W, stream, mesh, steps, nbands=8, band=3):
     return out
 
 
-def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8)):
+def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lanes=4):
     """Continuous-batching server: capacity from a closed loop, then Poisson
-    arrivals at rho * capacity; latency = submit -> result on the host.  The
+    arrivals at rho * capacity; latency = scheduled arrival -> result on the
+    host (the server stamps each request with its arrival time).  The
     warm-up closed loop is as large as the capacity run, so that the server's
     input pool already holds a buffer for every request in flight (a steady
     state server's pool does)."""
@@ -372,7 +373,7 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8)):
     reqs = W.served_requests(n_req)
     mean_t = float(np.mean([m.nt for m in reqs]))
     ctx = gp.Context(0)
-    srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=3)
+    srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=n_lanes)
 
     def closed_loop(n):
         ts = [srv.submit(reqs[i % n_req].xy, reqs[i % n_req].tri) for i in range(n)]
@@ -384,7 +385,7 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8)):
     closed_loop(cap_n)
     cap = srv.stats()["mtri_s"]
     out = {"requests": n_req, "mean_triangles": round(mean_t), "distinct_meshes": len({id(m) for m in reqs}),
-           "capacity_mtri_s": round(cap, 1), "lanes": 3, "max_batch": 32, "runs": []}
+           "capacity_mtri_s": round(cap, 1), "lanes": n_lanes, "max_batch": 32, "runs": []}
     for k, rho in enumerate(rhos):
         lam = rho * cap * 1e6 / mean_t
         gaps = W.poisson_gaps(n_req, lam, seed=5 + k)
@@ -400,21 +401,33 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8)):
 
         th = threading.Thread(target=waiter)
         th.start()
-        t0 = time.perf_counter()
-        at = t0
+        # arrivals on the monotonic clock the server stamps with: each
+        # request's latency runs from its scheduled arrival, so a submit that
+        # falls behind the schedule (or its input copy) is counted
+        at = time.monotonic_ns()
+        lags = np.empty(n_req)
+        first = last = 0
         for i in range(n_req):
-            at += gaps[i]
-            d = at - time.perf_counter()
+            at += int(gaps[i] * 1e9)
+            d = (at - time.monotonic_ns()) * 1e-9
             if d > 0:
                 time.sleep(d)
-            tq.put(srv.submit(reqs[i].xy, reqs[i].tri))
+            now = time.monotonic_ns()
+            lags[i] = (now - at) * 1e-6
+            first = now if i == 0 else first
+            last = now
+            tq.put(srv.submit(reqs[i].xy, reqs[i].tri, arrival_ns=at))
         tq.put(None)
         th.join()
         st = srv.stats()
-        out["runs"].append({"rho": rho, "rate_per_s": round(lam, 1), "completed": st["completed"],
+        out["runs"].append({"rho": rho, "rate_per_s": round(lam, 1),
+                            "achieved_rate_per_s": round((n_req - 1) / ((last - first) * 1e-9), 1),
+                            "max_lag_ms": round(float(lags.max()), 3), "mean_lag_ms": round(float(lags.mean()), 3),
+                            "completed": st["completed"],
                             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                             "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
-                            "mtri_s": round(st["mtri_s"], 1), "batches": st["batches"]})
+                            "mtri_s": round(st["mtri_s"], 1), "batches": st["batches"],
+                            "latency_from": "scheduled arrival"})
     srv.stop()
     ctx.close()
     return out

@@ -296,7 +296,7 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, completed, rejected, failed, batches, in_flight;
-    double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> result on the host */
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* arrival (or submit) -> result on the host */
     double mtri_s;                            /* triangles completed per second, first submit to last result */
 } gp_serve_stats;
 
@@ -304,8 +304,8 @@ typedef struct {
  * Starts a server on the device of ctx (whose launch shapes it copies).  The
  * server owns its own streams, threads and device memory: n_lanes lanes,
  * each with a stream, a host thread and an arena of pool_bytes / n_lanes
- * bytes.  Submitted inputs are copied into host buffers that the server
- * reuses after requests complete.  A request is admitted into a batch when the
+ * bytes.  Submitted inputs are copied into pinned host buffers that the
+ * server reuses after requests complete (at most 4 GiB of them kept free).  A request is admitted into a batch when the
  * exact device footprint of the batch (every half-edge build plus the
  * batched meshing run) fits a lane's arena.  Batches on different lanes
  * overlap; requests that arrive while batches run join the next free lane
@@ -317,6 +317,13 @@ int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out
  * GP_EAGAIN (queue full).  Thread-safe. */
 int gpolylla_serve_submit(gp_server *srv, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
                           uint64_t *ticket);
+/* The same, for a request that arrived at arrival_ns (CLOCK_MONOTONIC
+ * nanoseconds, the clock of std::chrono::steady_clock and of Python's
+ * time.monotonic_ns): its latency runs from then, so time the caller spent
+ * before submitting (its own queueing, the copy of the inputs) is counted.
+ * arrival_ns <= 0: now.  GP_EINVAL for an arrival in the future. */
+int gpolylla_serve_submit_at(gp_server *srv, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
+                             int64_t arrival_ns, uint64_t *ticket);
 /* Waits for a ticket (timeout_ms < 0: forever).  On success *out is a
  * host-resident result (gpolylla_result_info / _copy / _free work on it;
  * gpolylla_result_device does not).  Returns the request's status (its build

@@ -128,6 +128,8 @@ def _load():
         "gpolylla_serve_start": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_opts), ctypes.POINTER(_P)]),
         "gpolylla_serve_submit": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                                  ctypes.POINTER(ctypes.c_uint64)]),
+        "gpolylla_serve_submit_at": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int64,
+                                                    ctypes.POINTER(ctypes.c_uint64)]),
         "gpolylla_serve_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(_P)]),
         "gpolylla_serve_stats": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_stats)]),
         "gpolylla_serve_reset_stats": (ctypes.c_int, [_P]),
@@ -156,7 +158,7 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
             "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_mesh_jobs",
-            "gpolylla_serve_start", "gpolylla_serve_submit",
+            "gpolylla_serve_start", "gpolylla_serve_submit", "gpolylla_serve_submit_at",
             "gpolylla_serve_wait", "gpolylla_serve_stats", "gpolylla_serve_reset_stats", "gpolylla_serve_stop"]
 
 
@@ -343,6 +345,16 @@ def gpolylla_serve_submit(srv, xy, tri) -> int:
     return int(t.value)
 
 
+def gpolylla_serve_submit_at(srv, xy, tri, arrival_ns: int) -> int:
+    """Submits a request that arrived at arrival_ns (time.monotonic_ns())."""
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
+    tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32).reshape(-1, 3))
+    t = ctypes.c_uint64()
+    _check(_load().gpolylla_serve_submit_at(srv, xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
+                                            int(arrival_ns), ctypes.byref(t)), "gpolylla_serve_submit_at")
+    return int(t.value)
+
+
 def gpolylla_serve_wait(srv, ticket: int, timeout_ms: int = -1):
     out = _P()
     _check(_load().gpolylla_serve_wait(srv, ticket, timeout_ms, ctypes.byref(out)), "gpolylla_serve_wait")
@@ -421,7 +433,11 @@ class Server:
         self.handle = gpolylla_serve_start(ctx.handle, gp_serve_opts(pool_bytes, max_batch, max_queue, n_lanes))
         self._ctx = ctx
 
-    def submit(self, xy, tri) -> int:
+    def submit(self, xy, tri, arrival_ns: int = 0) -> int:
+        """arrival_ns: when the request arrived (time.monotonic_ns()); its
+        latency runs from then.  0: now."""
+        if arrival_ns:
+            return gpolylla_serve_submit_at(self.handle, xy, tri, arrival_ns)
         return gpolylla_serve_submit(self.handle, xy, tri)
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> Result:

@@ -29,7 +29,8 @@ namespace {
 
 struct Request {
     uint64_t ticket = 0;
-    std::vector<int32_t> xy, tri;
+    int32_t *xy = nullptr, *tri = nullptr;   // pinned copies of the inputs
+    size_t xy_cap = 0, tri_cap = 0;          // their blocks' real sizes
     int32_t nv = 0, nt = 0;
     size_t footprint = 0;   // build bytes; the batch adds its meshing bytes
     Clock::time_point t_submit;
@@ -87,34 +88,6 @@ struct PinnedPool {
     }
 };
 
-// Host buffers for requests' inputs, kept after a request completes and
-// handed to later submits: a reused buffer copies at memory speed, a fresh
-// one takes a page fault per page first.  At most kCap bytes are kept.
-struct InputPool {
-    static constexpr size_t kCap = (size_t)2 << 30;
-    std::mutex mu;
-    std::multimap<size_t, std::vector<int32_t>> free_;   // by capacity (elements)
-    size_t bytes = 0;
-    std::vector<int32_t> take(size_t n) {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = free_.lower_bound(n);
-        if (it == free_.end() || it->first > 2 * n + 4096) return {};
-        std::vector<int32_t> v = std::move(it->second);
-        bytes -= sizeof(int32_t) * it->first;
-        free_.erase(it);
-        return v;
-    }
-    void give(std::vector<int32_t> &&v) {
-        v.clear();
-        const size_t c = v.capacity();
-        if (!c) return;
-        std::lock_guard<std::mutex> lk(mu);
-        if (bytes + sizeof(int32_t) * c > kCap) return;   // dropped: freed with v
-        bytes += sizeof(int32_t) * c;
-        free_.emplace(c, std::move(v));
-    }
-};
-
 struct Lane {
     gp_ctx *ctx = nullptr;
     enum State { FREE, RUNNING, COPYING } state = FREE;
@@ -143,8 +116,10 @@ struct gp_server {
     gp_serve_opts opts{};
     size_t lane_bytes = 0;
     std::vector<Lane> lanes;
-    std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>();
-    InputPool inputs;
+    std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>();   // results
+    // requests' inputs: pinned, so that the builds' uploads are asynchronous
+    // copies at full link speed; reused after the requests complete
+    PinnedPool inputs;
     std::vector<std::thread> workers;   // one per lane
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -161,9 +136,14 @@ struct gp_server {
 
 namespace {
 
+void give_inputs(gp_server *s, Request *r) {
+    if (r->xy) s->inputs.give(r->xy, r->xy_cap);
+    if (r->tri) s->inputs.give(r->tri, r->tri_cap);
+    r->xy = r->tri = nullptr;
+}
+
 void complete(gp_server *s, Request *r, int status, gp_result *res) {
-    s->inputs.give(std::move(r->xy));   // the build has read them
-    s->inputs.give(std::move(r->tri));
+    give_inputs(s, r);   // the build has read them
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(s->mu);
     r->status = status;
@@ -184,15 +164,27 @@ void complete(gp_server *s, Request *r, int status, gp_result *res) {
 void launch(gp_server *s, Lane &L, std::vector<Request *> &batch) {
     L.reqs.clear();
     L.meshes.clear();
-    for (Request *r : batch) {
-        gp_mesh *m = nullptr;
-        const int rc = gpolylla_build_halfedges(L.ctx, r->xy.data(), r->nv, r->tri.data(), r->nt, 0, &m);
+    const int n = (int)batch.size();
+    std::vector<const int32_t *> xy(n), tri(n);
+    std::vector<int32_t> nv(n), nt(n);
+    std::vector<gp_mesh *> ms(n, nullptr);
+    std::vector<int> st(n, GP_OK);
+    for (int i = 0; i < n; i++) {
+        xy[i] = batch[i]->xy;
+        tri[i] = batch[i]->tri;
+        nv[i] = batch[i]->nv;
+        nt[i] = batch[i]->nt;
+    }
+    // every build of the batch, with two host checks in all
+    const int b = build_many(L.ctx, n, xy.data(), nv.data(), tri.data(), nt.data(), 0, ms.data(), st.data());
+    for (int i = 0; i < n; i++) {
+        const int rc = b != GP_OK ? b : st[i];
         if (rc != GP_OK) {
-            complete(s, r, rc, nullptr);
+            complete(s, batch[i], rc, nullptr);
             continue;
         }
-        L.reqs.push_back(r);
-        L.meshes.push_back(m);
+        L.reqs.push_back(batch[i]);
+        L.meshes.push_back(ms[i]);
     }
     if (L.reqs.empty()) {
         L.ctx->pool.reset();
@@ -401,10 +393,13 @@ int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out
     return GP_OK;
 }
 
-int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
-                          uint64_t *ticket) {
+int gpolylla_serve_submit_at(gp_server *s, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
+                             int64_t arrival_ns, uint64_t *ticket) {
     if (!s || !ticket || nv < 0 || nt < 0 || (nv > 0 && !xy) || (nt > 0 && !tri)) return GP_EINVAL;
     if (3ll * nt >= (1ll << 31)) return GP_ERANGE;
+    const auto now = Clock::now();
+    const auto arrival = Clock::time_point(std::chrono::nanoseconds(arrival_ns));
+    if (arrival_ns > 0 && arrival > now) return GP_EINVAL;   // not arrived yet
     Request *r = new (std::nothrow) Request();
     if (!r) return GP_ENOMEM;
     r->nv = nv;
@@ -412,7 +407,7 @@ int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int
     r->footprint = build_footprint(nv, nt, false);
     const int32_t one = nt;
     const size_t alone = r->footprint + batch_footprint(s->lanes[0].ctx->cfg, &one, 1);
-    r->t_submit = Clock::now();
+    r->t_submit = arrival_ns > 0 ? arrival : now;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {
@@ -430,13 +425,19 @@ int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int
             return GP_EAGAIN;
         }
     }
-    r->xy = s->inputs.take(2 * (size_t)nv);
-    r->tri = s->inputs.take(3 * (size_t)nt);
-    r->xy.assign(xy, xy + 2 * (size_t)nv);
-    r->tri.assign(tri, tri + 3 * (size_t)nt);
+    r->xy = static_cast<int32_t *>(s->inputs.take(8 * (size_t)nv, &r->xy_cap));
+    r->tri = static_cast<int32_t *>(s->inputs.take(12 * (size_t)nt, &r->tri_cap));
+    if (!r->xy || !r->tri) {
+        give_inputs(s, r);
+        delete r;
+        return GP_ENOMEM;
+    }
+    if (nv) std::memcpy(r->xy, xy, 8 * (size_t)nv);
+    if (nt) std::memcpy(r->tri, tri, 12 * (size_t)nt);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) {   // stopped while the inputs were copied: the lanes may be gone
+            give_inputs(s, r);
             delete r;
             return GP_EINVAL;
         }
@@ -452,6 +453,11 @@ int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int
     }
     s->cv_work.notify_one();
     return GP_OK;
+}
+
+int gpolylla_serve_submit(gp_server *s, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt,
+                          uint64_t *ticket) {
+    return gpolylla_serve_submit_at(s, xy, nv, tri, nt, 0, ticket);
 }
 
 int gpolylla_serve_wait(gp_server *s, uint64_t ticket, int32_t timeout_ms, gp_result **out) {

@@ -191,3 +191,26 @@ def test_two_waiters_on_one_ticket(ctx):
         got[0].free()
         for k in KEYS:
             assert np.array_equal(g[k], getattr(o, k)), k
+
+
+def test_latency_runs_from_the_arrival(ctx):
+    """A request submitted with an arrival 50 ms in the past reports a latency
+    of at least 50 ms; an arrival in the future is refused; the result is the
+    oracle's."""
+    import time
+    m = W.jittered_grid(20, seed=14)
+    o = oracle.polylla(m.xy, m.tri)
+    with gp.Server(ctx, pool_bytes=1 << 30, max_batch=4, n_lanes=1) as srv:
+        say("[gpu] serve: latency from the arrival time")
+        with pytest.raises(gp.GPolyllaError) as e:
+            srv.submit(m.xy, m.tri, arrival_ns=time.monotonic_ns() + 10**9)
+        assert e.value.code == gp.GP_EINVAL
+        srv.reset_stats()
+        t = srv.submit(m.xy, m.tri, arrival_ns=time.monotonic_ns() - 50 * 10**6)
+        r = srv.wait(t, 60000)
+        g = r.copy()
+        r.free()
+        for k in KEYS:
+            assert np.array_equal(g[k], getattr(o, k)), k
+        st = srv.stats()
+        assert st["completed"] == 1 and st["p50_ms"] >= 50.0
