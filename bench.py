@@ -300,12 +300,14 @@ def bench_pipeline(gp, W, stream, big):
     return out
 
 
-def _graph_form(gp, stream, m, steps):
-    """Graph-replay time of the meshing chain on mesh m (inputs resident),
-    its counts, and per-kernel times from a profiled pass."""
+def _graph_form(gp, stream, m, steps, bflags=0):
+    """Graph-replay time of the meshing chain on mesh m (inputs resident,
+    built with bflags), its counts, the mesh's resident bytes, and per-kernel
+    times from a profiled pass."""
     import torch
     ctx = gp.Context(0, stream=stream.cuda_stream)
-    h = ctx.build_halfedges(m.xy, m.tri)
+    h = ctx.build_halfedges(m.xy, m.tri, bflags)
+    mesh_bytes, escapes = h.nbytes()
     flags = gp.GP_ASYNC | gp.GP_GRAPH
     for _ in range(3):
         ctx.mesh(h, flags).free()
@@ -322,7 +324,7 @@ def _graph_form(gp, stream, m, steps):
     info = r.info()
     r.free()
     pctx = gp.Context(0, stream=stream.cuda_stream, profile=True)
-    ph = pctx.build_halfedges(m.xy, m.tri)
+    ph = pctx.build_halfedges(m.xy, m.tri, bflags)
     for _ in range(max(3, steps // 2)):
         pctx.mesh(ph, gp.GP_ASYNC).free()
     pctx.sync()
@@ -333,7 +335,23 @@ def _graph_form(gp, stream, m, steps):
     ctx.close()
     return {"workload": m.name, "triangles": m.nt, "vertices": m.nv, "polygons": info["npoly"],
             "loop_half_edges": info["nloop_he"], "tips": info["ntips"], "ms_per_step": round(ms, 4),
-            "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms}
+            "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms,
+            "mesh_bytes": mesh_bytes, "mesh_bytes_per_triangle": round(mesh_bytes / max(m.nt, 1), 2),
+            "escapes": escapes}
+
+
+def bench_compact(gp, stream, mesh, steps):
+    """The headline mesh in both resident encodings: int32 corners and twins,
+    and the compact one (16-bit offsets and an escape table; the direction the
+    paper names for bigger meshes): device bytes per triangle and Mtri/s of the
+    same meshing chain."""
+    out = {}
+    for name, flags in (("int32", 0), ("compact", gp.GP_COMPACT)):
+        r = _graph_form(gp, stream, mesh, steps, flags)
+        out[name] = {k: r[k] for k in ("ms_per_step", "mtri_s", "mesh_bytes", "mesh_bytes_per_triangle", "escapes")}
+    out["bytes_ratio"] = round(out["compact"]["mesh_bytes"] / out["int32"]["mesh_bytes"], 3)
+    out["speed_ratio"] = round(out["compact"]["mtri_s"] / out["int32"]["mtri_s"], 3)
+    return out
 
 
 def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
@@ -574,7 +592,7 @@ def main():
         chain_traffic = sum(chain_rec[k.split("<")[0]]["fetch_bytes"] + chain_rec[k.split("<")[0]]["write_bytes"]
                             for k in kms)
 
-    batched = served = delaunay = transfers = band = pipeline = None
+    batched = served = delaunay = transfers = band = pipeline = compact = None
     if not args.no_forms:
         log("[bench] one row band of an 8-way split (two halo rows)")
         band = bench_band(gp, W, stream, mesh, max(5, args.steps // 2))
@@ -584,6 +602,9 @@ def main():
         log(f"[bench] {transfers}")
         log("[bench] overlapped host-to-host pipeline")
         pipeline = bench_pipeline(gp, W, stream, mesh)
+        log("[bench] compact encoding of the headline mesh")
+        compact = bench_compact(gp, stream, mesh, max(5, args.steps // 2))
+        log(f"[bench] {compact}")
         log("[bench] general-position workload (Delaunay, 1M points)")
         delaunay = bench_delaunay(gp, W, stream, max(5, args.steps // 2))
         log(f"[bench] {delaunay}")
@@ -640,6 +661,7 @@ def main():
         "band": band,
         "transfers": transfers,
         "pipeline": pipeline,
+        "compact": compact,
         "cpu_baseline": cpu,
     }
     if cpu:

@@ -64,6 +64,7 @@ extern "C" {
 
 /* ---- flags -------------------------------------------------------------- */
 #define GP_IN_DEVICE 0x1u     /* build: xy and tri are device pointers on the context's device */
+#define GP_COMPACT 0x8u       /* build: keep the mesh in the compact encoding (gpolylla_build_halfedges) */
 #define GP_ASYNC 0x2u         /* mesh: return once the work is queued; counts are read
                                  (and errors reported) by the first result query */
 #define GP_GRAPH 0x4u         /* mesh: replay a captured hipGraph of the kernel chain; the
@@ -154,13 +155,25 @@ int gpolylla_ctx_get_launch(const gp_ctx *ctx, char *buf, int32_t cap);
  * share cache lines and tiles.  A randomly numbered 33.5M-triangle grid
  * meshes about 9x slower than the same grid numbered by rows; results are
  * the same either way, up to ties, which the numbering breaks.
+ * GP_COMPACT keeps the mesh in a narrower encoding, for bigger meshes per
+ * device (the direction Section 8 names for future work): per triangle its
+ * first corner (int32) and the other two as 16-bit offsets from it, per
+ * half-edge its twin as a 16-bit offset from itself, and the few values
+ * whose offsets do not fit in a hash table.  About 14 bytes per triangle
+ * instead of 24 (xy unchanged); every meshing call gives the same results
+ * as with the int32 arrays.
  */
 int gpolylla_build_halfedges(gp_ctx *ctx, const int32_t *xy, int32_t nv, const int32_t *tri,
                              int32_t nt, uint32_t flags, gp_mesh **out);
-/* Copies the oriented corner list (org, 3*nt) and twins (3*nt) to host buffers;
- * either may be NULL.  nflipped (may be NULL) receives the re-oriented count. */
+/* Copies the oriented corner list (org, 3*nt) and twins (3*nt) to host buffers
+ * (decoded, for a compact mesh); either may be NULL.  nflipped (may be NULL)
+ * receives the re-oriented count. */
 int gpolylla_mesh_copy(const gp_mesh *mesh, int32_t *org, int32_t *twin, int64_t *nflipped);
 int gpolylla_mesh_size(const gp_mesh *mesh, int32_t *nv, int32_t *nt);
+/* Device bytes the mesh holds (coordinates, corners, twins; in a compact
+ * mesh the escape table too); escapes (may be NULL) receives the number of
+ * escaped values of a compact mesh (0 otherwise). */
+int gpolylla_mesh_bytes(const gp_mesh *mesh, size_t *bytes, int64_t *escapes);
 void gpolylla_mesh_free(gp_mesh *mesh);
 
 /* ---- meshing ------------------------------------------------------------ */

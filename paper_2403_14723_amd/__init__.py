@@ -23,6 +23,7 @@ GP_OK = 0
 GP_EINVAL, GP_ERANGE, GP_EDEGEN, GP_ENONMANIFOLD, GP_ENOMEM, GP_EHIP = -1, -2, -3, -4, -5, -6
 GP_EAGAIN, GP_ETOOBIG, GP_ETIMEDOUT, GP_ECORRUPT = -7, -8, -9, -10
 GP_IN_DEVICE = 0x1
+GP_COMPACT = 0x8
 GP_ASYNC = 0x2
 GP_GRAPH = 0x4
 GP_OUT_LOOPS = 0x10
@@ -114,6 +115,7 @@ def _load():
                                                     ctypes.c_uint32, ctypes.POINTER(_P)]),
         "gpolylla_mesh_copy": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
         "gpolylla_mesh_size": (ctypes.c_int, [_P, _I32P, _I32P]),
+        "gpolylla_mesh_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64)]),
         "gpolylla_mesh_free": (None, [_P]),
         "gpolylla_mesh": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
         "gpolylla_mesh_batch": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_uint32,
@@ -155,7 +157,8 @@ def exported_symbols() -> list[str]:
 _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", "gpolylla_ctx_pool_bytes",
             "gpolylla_ctx_sync", "gpolylla_ctx_kernel_ms", "gpolylla_ctx_kernel_reset",
             "gpolylla_ctx_set_launch", "gpolylla_ctx_get_launch",
-            "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_free",
+            "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_bytes",
+            "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
             "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_mesh_jobs",
             "gpolylla_serve_start", "gpolylla_serve_submit", "gpolylla_serve_submit_at",
@@ -385,6 +388,12 @@ class Mesh:
 
     def copy(self):
         return gpolylla_mesh_copy(self.handle)
+
+    def nbytes(self) -> tuple[int, int]:
+        """(device bytes the mesh holds, escaped values of a compact mesh)"""
+        b, e = ctypes.c_size_t(), ctypes.c_int64()
+        _check(_load().gpolylla_mesh_bytes(self.handle, ctypes.byref(b), ctypes.byref(e)), "gpolylla_mesh_bytes")
+        return b.value, e.value
 
     def free(self):
         if self.handle:

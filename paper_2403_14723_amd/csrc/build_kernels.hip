@@ -294,6 +294,111 @@ __global__ void k_match(const int32_t *__restrict__ org, int nt, const int32_t *
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// compact half-edge encoding
+// ---------------------------------------------------------------------------
+
+// 16-bit offset of v from base, or kEsc16 when it does not fit (or is 0 and
+// zero is reserved: twins, where 0 means boundary).
+__device__ __forceinline__ int off16(int v, int base, bool zero_reserved) {
+    const int d = v - base;
+    return (d > kEsc16 && d <= 32767 && !(zero_reserved && d == 0)) ? d : kEsc16;
+}
+
+// One thread per triangle: its record and its three twin offsets; the
+// escapes are counted (one atomic per wave that has any).
+__global__ void __launch_bounds__(256) k_compact_encode(const int32_t *__restrict__ org,
+                                                        const int32_t *__restrict__ twin, int nt, int2 *org8,
+                                                        int16_t *twin16, int32_t *nesc) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = 0;
+    if (t < nt) {
+        const int v0 = org[3 * t], v1 = org[3 * t + 1], v2 = org[3 * t + 2];
+        const int d1 = off16(v1, v0, false), d2 = off16(v2, v0, false);
+        n += (d1 == kEsc16) + (d2 == kEsc16);
+        org8[t] = make_int2(v0, (d1 & 0xffff) | (d2 << 16));
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            const int h = 3 * t + i, g = twin[h];
+            const int d = g < 0 ? 0 : off16(g, h, true);
+            n += d == kEsc16;
+            twin16[h] = (int16_t)d;
+        }
+    }
+    const unsigned long long any = __ballot(n != 0);
+    if (any) {
+        int w = n;
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+        if (__lane_id() == __ffsll((long long)any) - 1) atomicAdd(nesc, w);
+    }
+}
+
+__device__ __forceinline__ void esc_insert(int32_t *esc, int32_t mask, int32_t key, int32_t val) {
+    uint32_t slot = esc_hash(key) & (uint32_t)mask;
+    for (int k = 0; k <= mask; k++) {
+        const int32_t prev = atomicCAS(esc + 2 * slot, kEscEmpty, key);
+        if (prev == kEscEmpty || prev == key) {
+            esc[2 * slot + 1] = val;
+            return;
+        }
+        slot = (slot + 1) & (uint32_t)mask;
+    }
+}
+
+__global__ void k_esc_clear(int32_t *esc, int n) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+        esc[k] = (k & 1) ? 0 : kEscEmpty;
+}
+
+// Every value the encoder could not fit goes into the table.
+__global__ void __launch_bounds__(256) k_compact_escapes(const int32_t *__restrict__ org,
+                                                         const int32_t *__restrict__ twin, int nt, int32_t *esc,
+                                                         int32_t mask) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int v0 = org[3 * t];
+#pragma unroll
+    for (int i = 1; i < 3; i++) {
+        const int v = org[3 * t + i];
+        if (off16(v, v0, false) == kEsc16) esc_insert(esc, mask, ~(3 * t + i), v);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int h = 3 * t + i, g = twin[h];
+        if (g >= 0 && off16(g, h, true) == kEsc16) esc_insert(esc, mask, h, g);
+    }
+}
+
+__device__ __forceinline__ int32_t esc_get(const int32_t *esc, int32_t mask, int32_t key) {
+    uint32_t slot = esc_hash(key) & (uint32_t)mask;
+    for (int k = 0; k <= mask; k++) {
+        const int32_t kk = esc[2 * slot];
+        if (kk == key) return esc[2 * slot + 1];
+        if (kk == kEscEmpty) break;
+        slot = (slot + 1) & (uint32_t)mask;
+    }
+    return -1;
+}
+
+__global__ void __launch_bounds__(256) k_compact_decode(const int2 *__restrict__ org8,
+                                                        const int16_t *__restrict__ twin16,
+                                                        const int32_t *__restrict__ esc, int32_t mask, int nt,
+                                                        int32_t *org, int32_t *twin) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int2 r = org8[t];
+    const int d[3] = {0, (int)(int16_t)(r.y & 0xffff), r.y >> 16};
+    org[3 * t] = r.x;
+#pragma unroll
+    for (int i = 1; i < 3; i++) org[3 * t + i] = d[i] == kEsc16 ? esc_get(esc, mask, ~(3 * t + i)) : r.x + d[i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const int h = 3 * t + i, v = twin16[h];
+        twin[h] = v == 0 ? -1 : (v == kEsc16 ? esc_get(esc, mask, h) : h + v);
+    }
+}
+
 inline int grid_for(long long n, int block, int cap = 1 << 16) {
     long long g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -327,6 +432,29 @@ hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s) {
         hipLaunchKernelGGL(k_match, dim3(grid_for(nh, 256)), dim3(256), 0, s, b.org, b.nt, b.vstart,
                            b.bucket, b.twin, b.err_key);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_encode(const CompactBuffers &c, hipStream_t s) {
+    if (c.nt > 0)
+        hipLaunchKernelGGL(k_compact_encode, dim3((c.nt + 255) / 256), dim3(256), 0, s, c.org, c.twin, c.nt, c.org8,
+                           c.twin16, c.nesc);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_escapes(const CompactBuffers &c, hipStream_t s) {
+    const long long n = 2ll * ((long long)c.esc_mask + 1);
+    hipLaunchKernelGGL(k_esc_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, c.esc, (int)n);
+    if (c.nt > 0)
+        hipLaunchKernelGGL(k_compact_escapes, dim3((c.nt + 255) / 256), dim3(256), 0, s, c.org, c.twin, c.nt, c.esc,
+                           c.esc_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_decode(const CompactBuffers &c, int32_t *org, int32_t *twin, hipStream_t s) {
+    if (c.nt > 0)
+        hipLaunchKernelGGL(k_compact_decode, dim3((c.nt + 255) / 256), dim3(256), 0, s, c.org8, c.twin16, c.esc,
+                           c.esc_mask, c.nt, org, twin);
     return hipGetLastError();
 }
 

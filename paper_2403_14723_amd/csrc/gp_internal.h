@@ -63,7 +63,13 @@ struct MeshDesc {
     int32_t tri_tile0;   // first tile of this mesh in the triangle tile space
     int32_t he_tile0;    // first tile of this mesh in the relink tile space (triangles)
     int32_t cmp_tile0;   // first tile of this mesh in the compaction tile space
-    int32_t pad;
+    int32_t esc_mask;    // compact meshes: escape table slots - 1
+    // compact meshes (org and twin are null): per triangle {v0, (v1 - v0) |
+    // (v2 - v0) << 16} and per half-edge twin - h as int16 (0: boundary);
+    // a 16-bit field holding kEsc16 is in the escape table
+    const int2 *org8;
+    const int16_t *twin16;
+    const int32_t *esc;  // (key, value) pairs: key h for a twin, ~h for corner h
 };
 
 static_assert(sizeof(MeshDesc) % 4 == 0, "descriptor tables are copied in 4-byte words");
@@ -99,6 +105,7 @@ struct LaunchCfg {
 struct RunBuffers {
     const MeshDesc *descs;   // device, nmesh entries
     int nmesh;
+    bool compact;            // some mesh is in the compact encoding
     int32_t tri_tiles;       // total triangle tiles (label)
     int32_t he_tiles;        // total relink tiles
     int32_t cmp_tiles;       // total compaction tiles
@@ -184,5 +191,38 @@ struct BuildBuffers {
 hipError_t launch_build_orient(const BuildBuffers &b, hipStream_t s);
 hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s);
 int32_t build_scan_tiles(int32_t n);
+
+// ---- compact half-edge encoding (build_kernels.hip) ----------------------
+//
+// A compact mesh keeps its corners and twins in 16-bit offsets: the twin of
+// h as twin - h, the corners of a triangle as v0 plus v1 - v0 and v2 - v0.
+// Values whose offset does not fit (or is 0 for a twin, which means
+// boundary) are kept in an open-addressing hash table of (key, value) pairs:
+// key h for the twin of h, ~h for corner h (the org of half-edge h).
+
+constexpr int kEsc16 = -32768;               // the value is in the escape table
+constexpr int32_t kEscEmpty = (int32_t)0x80000000u;   // an empty table slot
+
+__host__ __device__ inline uint32_t esc_hash(int32_t key) {
+    uint32_t x = (uint32_t)key * 0x9E3779B1u;
+    return x ^ (x >> 15);
+}
+
+struct CompactBuffers {
+    const int32_t *org, *twin;   // the int32 structure (input of the encoder)
+    int32_t nt;
+    int2 *org8;
+    int16_t *twin16;
+    int32_t *esc;                // 2 * (esc_mask + 1) ints
+    int32_t esc_mask;
+    int32_t *nesc;               // escapes counted by the encoder
+};
+
+// org8 and twin16, and the number of escapes into *nesc (zeroed by the caller)
+hipError_t launch_compact_encode(const CompactBuffers &c, hipStream_t s);
+// the escape table (cleared, then filled); needs esc and esc_mask
+hipError_t launch_compact_escapes(const CompactBuffers &c, hipStream_t s);
+// org and twin (int32) decoded from org8, twin16 and the table
+hipError_t launch_compact_decode(const CompactBuffers &c, int32_t *org, int32_t *twin, hipStream_t s);
 
 }  // namespace gp

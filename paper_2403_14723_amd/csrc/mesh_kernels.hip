@@ -57,6 +57,39 @@ typedef int v3i __attribute__((ext_vector_type(3)));
 // three ints at 4-byte alignment (a v3i claims 16): loads of 12-byte records
 typedef int v3i_a4 __attribute__((ext_vector_type(3), aligned(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Value of escaped field key of a compact mesh (the table holds every key an
+// escaped field can ask for; -1 for an absent key: a corrupt table).
+__device__ __forceinline__ int esc_lookup(const int32_t *__restrict__ esc, int32_t mask, int32_t key) {
+    uint32_t slot = esc_hash(key) & (uint32_t)mask;
+    for (int k = 0; k <= mask; k++) {
+        const int32_t kk = esc[2 * slot];
+        if (kk == key) return esc[2 * slot + 1];
+        if (kk == kEscEmpty) break;
+        slot = (slot + 1) & (uint32_t)mask;
+    }
+    return -1;
+}
+
+// Twins of a mesh, in either encoding: twin[h] (-1 on the boundary).  The
+// encoding is the same for every lane of a launch over one mesh, so the
+// branch on it is uniform.
+struct TwinView {
+    GLOBAL const int32_t *t32;
+    GLOBAL const int16_t *t16;   // compact: twin - h (0: boundary, kEsc16: escaped)
+    const int32_t *esc;
+    int32_t mask;
+    __device__ __forceinline__ int operator[](int h) const {
+        if (!t16) return t32[h];
+        const int v = t16[h];
+        if (v == 0) return -1;
+        return v != kEsc16 ? h + v : esc_lookup(esc, mask, h);
+    }
+};
+
+__device__ __forceinline__ TwinView twin_view(const MeshDesc &d) {
+    return TwinView{(GLOBAL const int32_t *)d.twin, (GLOBAL const int16_t *)d.twin16, d.esc, d.esc_mask};
+}
 typedef GLOBAL const v2i *gcv2i;
 
 // ---------------------------------------------------------------------------
@@ -91,8 +124,7 @@ __device__ __forceinline__ bool is_frontier(const uint8_t *__restrict__ tflag, i
 // linked, c <- next(twin(c)); !NEXT: the mirror, c <- prev(twin(c)).  A
 // non-frontier edge is interior, so twin(c) exists.  -1 when the guard trips.
 template <bool NEXT>
-__device__ __forceinline__ int turn(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag, int c,
-                                    uint32_t fc) {
+__device__ __forceinline__ int turn(const TwinView &twin, const uint8_t *__restrict__ tflag, int c, uint32_t fc) {
     for (int k = 0; k < kRotGuard; k++) {
         const int tc = c / 3;
         if (fbit(fc, c - 3 * tc)) return c;
@@ -104,13 +136,11 @@ __device__ __forceinline__ int turn(const int32_t *__restrict__ twin, const uint
     return -1;
 }
 
-__device__ __forceinline__ int turn_next(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag,
-                                         int h) {
+__device__ __forceinline__ int turn_next(const TwinView &twin, const uint8_t *__restrict__ tflag, int h) {
     const int c = he_next(h);
     return turn<true>(twin, tflag, c, tflag[c / 3]);
 }
-__device__ __forceinline__ int turn_prev(const int32_t *__restrict__ twin, const uint8_t *__restrict__ tflag,
-                                         int h) {
+__device__ __forceinline__ int turn_prev(const TwinView &twin, const uint8_t *__restrict__ tflag, int h) {
     const int c = he_prev(h);
     return turn<false>(twin, tflag, c, tflag[c / 3]);
 }
@@ -312,7 +342,19 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
     // triangle base + j*B + tid
     const int cnt_all = min(B * ITEMS, nt - base);
     if (cnt_all <= 0) return;   // an empty mesh's tile (the whole block)
-    load_to_lds<(3 * ITEMS + 3) / 4>(s_org, (gcint)(d.org) + 3 * (size_t)base, 3 * cnt_all);
+    if (!d.org8) {   // (uniform)
+        load_to_lds<(3 * ITEMS + 3) / 4>(s_org, (gcint)(d.org) + 3 * (size_t)base, 3 * cnt_all);
+    } else {   // a compact mesh: v0 and two 16-bit offsets per triangle
+        GLOBAL const v2i *o8 = (GLOBAL const v2i *)d.org8 + base;
+        for (int k = tid; k < cnt_all; k += B) {
+            const v2i r = o8[k];
+            const int d1 = (int)(int16_t)(r.y & 0xffff), d2 = r.y >> 16;
+            const int h = 3 * (base + k);
+            s_org[3 * k] = r.x;
+            s_org[3 * k + 1] = d1 != kEsc16 ? r.x + d1 : esc_lookup(d.esc, d.esc_mask, ~(h + 1));
+            s_org[3 * k + 2] = d2 != kEsc16 ? r.x + d2 : esc_lookup(d.esc, d.esc_mask, ~(h + 2));
+        }
+    }
     __syncthreads();
     // every corner of every item first, so all the gathers are in flight
     // together (items past the tile read corner 0 and are dropped)
@@ -344,7 +386,7 @@ __global__ void __launch_bounds__(1024) k_label(const MeshDesc *__restrict__ des
             const long long ls[3] = {l0, l1, l2};
             for (int i = 0; i < 3; i++) {
                 if (ls[i] != m) continue;
-                const int h = 3 * t + i, g = d.twin[h];
+                const int h = 3 * t + i, g = twin_view(d)[h];
                 const int id = (g >= 0 && g < h) ? g : h;
                 if (id < bid) {
                     bid = id;
@@ -421,7 +463,7 @@ __device__ __forceinline__ void store_bytes_from_lds(gu8 dst, const uint8_t *src
 // Frontier test of half-edge c during k_relink.  Lc is the longest-edge label
 // of c's triangle, or -1 when it has not been loaded.
 struct TileLabels {
-    gcint twin;
+    TwinView twin;
     gcu8 tflag;                          // longest-edge bits (0-1) only are read
     const int *s_tw;                     // the tile's twins
     const uint8_t *s_f;                  // the tile's label bytes, frontier bits set
@@ -503,7 +545,9 @@ __device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc)
     return (int)(T.tflag[tg] & 3u) != g - 3 * tg;
 }
 
-template <int ITEMS>
+// CM: some mesh of the run is compact (else the int32 twins are read
+// without a test of the encoding)
+template <int ITEMS, bool CM>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
                                                   RunCounters *rc, ListEntry *tips, int cap_tips,
                                                   ListEntry *walk, int32_t *walk_counts, int walk_cap,
@@ -533,7 +577,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     const int mi = find_mesh<1>(descs, nmesh, tile);
     const MeshDesc &d = descs[mi];
     const int nt = d.nt;
-    const gcint twin = (gcint)(d.twin);
+    TwinView twin = twin_view(d);
+    if (!CM) twin.t16 = nullptr;
     const gu8 tflag = (gu8)(d.tflag);
     const gint nxo = (gint)(d.next_o), pvo = (gint)(d.prev_o);
     const int base = (tile - d.he_tile0) * TB;
@@ -552,7 +597,15 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
     for (int j = 0; j < ITEMS; j++) {
         const int lt = j * B + tid;
         const bool ok = lt < cnt;
-        const v3i_a4 g = *(GLOBAL const v3i_a4 *)(twin + 3 * (size_t)(base + (ok ? lt : 0)));
+        const int hj = 3 * (base + (ok ? lt : 0));
+        v3i_a4 g;
+        if (!twin.t16) {   // (uniform) one 12-byte load
+            g = *(GLOBAL const v3i_a4 *)(twin.t32 + hj);
+        } else {
+            g.x = twin[hj];
+            g.y = twin[hj + 1];
+            g.z = twin[hj + 2];
+        }
         tw[j][0] = ok ? g.x : -1;
         tw[j][1] = ok ? g.y : -1;
         tw[j][2] = ok ? g.z : -1;
@@ -882,7 +935,7 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
             const ListEntry e = tips[k];
             mesh = e.mesh;
             const MeshDesc &d = descs[e.mesh];
-            const gcint twin = (gcint)d.twin;
+            const TwinView twin = twin_view(d);
             // a: the only frontier edge at the tip v = target(e.he), leaving v
             a = twin[e.he];
             bool err = a < 0;
@@ -952,7 +1005,7 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
 
 __device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
     // e leaves the vertex x; prev(e) enters x in the same triangle
-    const int32_t *__restrict__ twin = d.twin;
+    const TwinView twin = twin_view(d);
     const uint8_t *__restrict__ tflag = d.tflag;
     const int p = he_prev(e);
     bool ok = true;
@@ -987,7 +1040,7 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
         const bool valid = q < nfix;
         const ListEntry en = valid ? fixes[q] : ListEntry{0, 0};
         const MeshDesc &d = descs[en.mesh];
-        const gcint twin = (gcint)d.twin;
+        const TwinView twin = twin_view(d);
         const int o = en.he;
         bool ok = true, have = false, boundary = false;
         int e = o;
@@ -1065,7 +1118,7 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
     int f = s;
     for (int k = 0; k < kRotGuard; k++) {
         if (is_frontier(d.tflag, f)) return f;
-        const int g = d.twin[f];
+        const int g = twin_view(d)[f];
         if (g < 0) return -1;
         f = he_next(g);
     }
@@ -1613,6 +1666,22 @@ hipError_t launch_export_counts(const MeshCounters *c, int32_t *out, hipStream_t
         }                                                                                     \
     } while (0)
 
+template <bool CM>
+hipError_t launch_relink(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, size_t lds, int cmp_tb) {
+    const dim3 grid(rb.he_tiles), block(cfg.block_relink);
+#define GP_RELINK_ARGS rb.descs, rb.nmesh, rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, \
+                       rb.status, cmp_tb
+    switch (cfg.items_relink) {
+        case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<1, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<2, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<4, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<8, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef GP_RELINK_ARGS
+    return hipGetLastError();
+}
+
 hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, launch_hook hook,
                            void *user) {
     auto H = [&](int k, int after) {
@@ -1632,9 +1701,12 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_LABEL, 1);
 
     H(K_RELINK, 0);
-    GP_LAUNCH_ITEMS(k_relink, cfg.items_relink, dim3(rb.he_tiles), dim3(cfg.block_relink),
-                    (sizeof(int) * 3 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink, s, rb.descs, rb.nmesh,
-                    rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, rb.status, cmp_tb);
+    {
+        const size_t lds = (sizeof(int) * 3 + 2 + 4 + 1) * (size_t)cfg.block_relink * cfg.items_relink;
+        const hipError_t e = rb.compact ? launch_relink<true>(cfg, rb, s, lds, cmp_tb)
+                                        : launch_relink<false>(cfg, rb, s, lds, cmp_tb);
+        if (e != hipSuccess) return e;
+    }
     H(K_RELINK, 1);
 
     H(K_REPAIR, 0);

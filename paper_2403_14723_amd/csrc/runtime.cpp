@@ -254,15 +254,18 @@ int plan_core(const gp::LaunchCfg &cfg, const int32_t *nts, const int32_t *nvs, 
 struct Plan : PlanSizes {
     std::vector<gp::MeshDesc> descs;   // sizes and tile offsets filled in
     std::vector<int32_t> nts;
+    bool compact = false;              // some mesh is in the compact encoding
 };
 
 int make_plan(const gp::LaunchCfg &cfg, const gp_mesh *const *meshes, int n, Plan *p) {
     p->descs.assign(n, gp::MeshDesc{});
     p->nts.resize(n);
+    p->compact = false;
     std::vector<int32_t> nvs(n);
     for (int i = 0; i < n; i++) {
         p->nts[i] = meshes[i]->nt;
         nvs[i] = meshes[i]->nv;
+        p->compact |= meshes[i]->org8 != nullptr;
     }
     return plan_core(cfg, p->nts.data(), nvs.data(), n, p->descs.data(), p);
 }
@@ -421,8 +424,69 @@ int build_stage1(gp_ctx *c, BuildJob &j) {
 int build_stage2(gp_ctx *c, BuildJob &j) {
     if (*j.key_h != ~0ull) return -(int)(*j.key_h & 0xff);
     j.m->nflipped = *j.nflip_h;
+    j.m->bytes = align_up(sizeof(int2) * (size_t)std::max(j.m->nv, 1)) +
+                 2 * align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(3ll * j.m->nt, 1));
     c->pool.release(j.p_tmp);
     j.p_tmp = nullptr;
+    return GP_OK;
+}
+
+// Re-encodes a built mesh compactly (see gp::MeshDesc) and frees its int32
+// corners and twins.  host: 4 bytes of pinned scratch.
+int compact_mesh(gp_ctx *c, gp_mesh *m, int32_t *host) {
+    const int64_t nt = m->nt, nh = 3 * nt;
+    void *p8 = nullptr, *p16 = nullptr, *pe = nullptr, *pn = nullptr;
+    int rc = c->pool.alloc(sizeof(int2) * (size_t)std::max<int64_t>(nt, 1), &p8);
+    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int16_t) * (size_t)std::max<int64_t>(nh, 1), &p16);
+    if (rc == GP_OK) rc = c->pool.alloc(sizeof(int32_t), &pn);
+    gp::CompactBuffers cb{};
+    cb.org = m->org;
+    cb.twin = m->twin;
+    cb.nt = m->nt;
+    cb.org8 = static_cast<int2 *>(p8);
+    cb.twin16 = static_cast<int16_t *>(p16);
+    cb.nesc = static_cast<int32_t *>(pn);
+    hipStream_t s = c->stream;
+    if (rc == GP_OK &&
+        (hipMemsetAsync(cb.nesc, 0, sizeof(int32_t), s) != hipSuccess ||
+         gp::launch_compact_encode(cb, s) != hipSuccess ||
+         hipMemcpyAsync(host, cb.nesc, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = GP_EHIP;
+    }
+    int32_t slots = 2;   // a power of two at least twice the escapes
+    if (rc == GP_OK) {
+        while (slots < 2 * (int64_t)*host) slots *= 2;
+        rc = c->pool.alloc(2 * sizeof(int32_t) * (size_t)slots, &pe);
+    }
+    cb.esc = static_cast<int32_t *>(pe);
+    cb.esc_mask = slots - 1;
+    if (rc == GP_OK &&
+        (gp::launch_compact_escapes(cb, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = GP_EHIP;
+    }
+    c->pool.release(pn);
+    if (rc != GP_OK) {
+        (void)hipStreamSynchronize(s);
+        c->pool.release(p8);
+        c->pool.release(p16);
+        c->pool.release(pe);
+        return rc;
+    }
+    m->nesc = *host;
+    c->pool.release(m->org);
+    c->pool.release(m->twin);
+    m->org = m->twin = nullptr;
+    m->org8 = cb.org8;
+    m->twin16 = cb.twin16;
+    m->esc = cb.esc;
+    m->esc_mask = cb.esc_mask;
+    m->bytes = align_up(sizeof(int2) * (size_t)std::max(m->nv, 1)) +
+               align_up(sizeof(int2) * (size_t)std::max<int64_t>(nt, 1)) +
+               align_up(sizeof(int16_t) * (size_t)std::max<int64_t>(nh, 1)) +
+               align_up(2 * sizeof(int32_t) * (size_t)slots);
     return GP_OK;
 }
 
@@ -453,6 +517,9 @@ int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, co
     drain();
     for (BuildJob &j : jobs)
         if (j.rc == GP_OK) j.rc = build_stage2(c, j);
+    if (flags & GP_COMPACT)
+        for (BuildJob &j : jobs)
+            if (j.rc == GP_OK) j.rc = compact_mesh(c, j.m, j.nflip_h);
     // a failed job's memory goes back after the stream has drained its work
     bool failed = false;
     for (BuildJob &j : jobs) failed |= j.rc != GP_OK;
@@ -497,6 +564,7 @@ namespace {
 struct GraphEntry {
     gp::LaunchCfg cfg;
     std::vector<int32_t> nts;
+    bool compact = false;
     void *scratch = nullptr;
     gp::RunBuffers rb{};
     std::vector<uint8_t *> tflag, pl;
@@ -531,7 +599,7 @@ void graph_entry_free(gp_ctx *c, GraphEntry &e) {
 int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     GraphCache &gc = graphs_of(c);
     for (auto &e : gc.entries) {
-        if (e.nts == plan.nts && same_cfg(e.cfg, c->cfg)) {
+        if (e.nts == plan.nts && e.compact == plan.compact && same_cfg(e.cfg, c->cfg)) {
             e.last_use = ++gc.tick;
             *out = &e;
             return GP_OK;
@@ -547,6 +615,7 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     GraphEntry e;
     e.cfg = c->cfg;
     e.nts = plan.nts;
+    e.compact = plan.compact;
     int rc = c->pool.alloc(plan.tmp_bytes, &e.scratch);
     if (rc != GP_OK) return rc;
     const int n = (int)plan.nts.size();
@@ -554,6 +623,7 @@ int graph_entry(gp_ctx *c, const Plan &plan, GraphEntry **out) {
     e.pl.resize(n);
     e.lpos.resize(n);
     layout_scratch(plan, plan.descs.data(), n, e.scratch, &e.rb, e.tflag.data(), e.pl.data(), e.lpos.data());
+    e.rb.compact = plan.compact;
     hipGraph_t graph = nullptr;
     hipStream_t s = c->stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -847,9 +917,41 @@ int gpolylla_mesh_copy(const gp_mesh *m, int32_t *org, int32_t *twin, int64_t *n
     if (!m) return GP_EINVAL;
     DeviceGuard g(m->ctx->device);
     size_t n = sizeof(int32_t) * 3 * (size_t)m->nt;
-    if (org && n) HIP_OK(hipMemcpy(org, m->org, n, hipMemcpyDeviceToHost));
-    if (twin && n) HIP_OK(hipMemcpy(twin, m->twin, n, hipMemcpyDeviceToHost));
     if (nflipped) *nflipped = m->nflipped;
+    if (!n || (!org && !twin)) return GP_OK;
+    if (!m->org8) {
+        if (org) HIP_OK(hipMemcpy(org, m->org, n, hipMemcpyDeviceToHost));
+        if (twin) HIP_OK(hipMemcpy(twin, m->twin, n, hipMemcpyDeviceToHost));
+        return GP_OK;
+    }
+    // a compact mesh: decode into scratch first
+    gp_ctx *c = m->ctx;
+    void *p = nullptr;
+    int rc = c->pool.alloc(2 * align_up(n), &p);
+    if (rc != GP_OK) return rc;
+    int32_t *dorg = static_cast<int32_t *>(p);
+    int32_t *dtwin = reinterpret_cast<int32_t *>(static_cast<char *>(p) + align_up(n));
+    gp::CompactBuffers cb{};
+    cb.nt = m->nt;
+    cb.org8 = m->org8;
+    cb.twin16 = m->twin16;
+    cb.esc = m->esc;
+    cb.esc_mask = m->esc_mask;
+    if (gp::launch_compact_decode(cb, dorg, dtwin, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess ||
+        (org && hipMemcpy(org, dorg, n, hipMemcpyDeviceToHost) != hipSuccess) ||
+        (twin && hipMemcpy(twin, dtwin, n, hipMemcpyDeviceToHost) != hipSuccess)) {
+        (void)hipGetLastError();
+        rc = GP_EHIP;
+    }
+    c->pool.release(p);
+    return rc;
+}
+
+int gpolylla_mesh_bytes(const gp_mesh *m, size_t *bytes, int64_t *escapes) {
+    if (!m) return GP_EINVAL;
+    if (bytes) *bytes = m->bytes;
+    if (escapes) *escapes = m->nesc;
     return GP_OK;
 }
 
@@ -867,6 +969,9 @@ void gpolylla_mesh_free(gp_mesh *m) {
     m->ctx->pool.release(m->xy);
     m->ctx->pool.release(m->org);
     m->ctx->pool.release(m->twin);
+    m->ctx->pool.release(m->org8);
+    m->ctx->pool.release(m->twin16);
+    m->ctx->pool.release(m->esc);
     delete m;
 }
 
@@ -933,6 +1038,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         lpos = ge->lpos;
     } else {
         layout_scratch(plan, plan.descs.data(), n, p_tmp, &rb, tflag.data(), pl.data(), lpos.data());
+        rb.compact = plan.compact;
     }
     Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
     std::vector<gp_result *> res(n, nullptr);
@@ -960,9 +1066,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         x->loop_off = ao.take<int32_t>(m->nt + 2);
         res[i] = x;
         gp::MeshDesc &d = descs[i];
-        d.xy = m->xy;
-        d.org = m->org;
-        d.twin = m->twin;
+        mesh_desc_fill(m, d);
         d.next_o = x->next_o;
         d.prev_o = x->prev_o;
         d.seeds = x->seeds;
@@ -1052,9 +1156,8 @@ int gpolylla_mesh_noalloc(gp_ctx *c, const gp_mesh *m, const gp_result_dev *out,
     uint8_t *tflag = nullptr, *pl = nullptr;
     int32_t *lpos = nullptr;
     layout_scratch(plan, &d, 1, base, &rb, &tflag, &pl, &lpos);
-    d.xy = m->xy;
-    d.org = m->org;
-    d.twin = m->twin;
+    rb.compact = m->org8 != nullptr;
+    mesh_desc_fill(m, d);
     d.next_o = out->next;
     d.prev_o = out->prev;
     d.seeds = out->seeds;

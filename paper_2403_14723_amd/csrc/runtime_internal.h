@@ -201,9 +201,27 @@ struct gp_mesh {
     int32_t nv = 0, nt = 0;
     int64_t nflipped = 0;
     int2 *xy = nullptr;
-    int32_t *org = nullptr;
-    int32_t *twin = nullptr;
+    int32_t *org = nullptr;    // null in a compact mesh
+    int32_t *twin = nullptr;   // null in a compact mesh
+    // compact meshes (GP_COMPACT): see gp::MeshDesc
+    int2 *org8 = nullptr;
+    int16_t *twin16 = nullptr;
+    int32_t *esc = nullptr;
+    int32_t esc_mask = 0;
+    int32_t nesc = 0;
+    size_t bytes = 0;          // device bytes the mesh holds
 };
+
+// The mesh's fields of a descriptor.
+inline void mesh_desc_fill(const gp_mesh *m, gp::MeshDesc &d) {
+    d.xy = m->xy;
+    d.org = m->org;
+    d.twin = m->twin;
+    d.org8 = m->org8;
+    d.twin16 = m->twin16;
+    d.esc = m->esc;
+    d.esc_mask = m->esc_mask;
+}
 
 namespace gprt {
 struct RunState {
