@@ -6,7 +6,7 @@ triangle within k vertex rings of P meshes its copy on its own.  For the
 half-edges of P the labels, the repaired frontier and next'/prev' must then be
 those of the whole mesh, so that only loops cut by a band boundary need a
 stitching step.  The repair (Section 6.4) adds the middle edge of each barrier
-tip, and next'/prev' (Section 6.3) turn around the target vertex, so an edge
+tip, and next'/prev' (Section 6.5) turn around the target vertex, so an edge
 incident to a band vertex can change because of a tip one ring further out:
 two rings are enough and one is not.
 """
