@@ -212,6 +212,37 @@ void gpolylla_result_free(gp_result *res);
 /* Waits until all queued work of the context has finished. */
 int gpolylla_ctx_sync(gp_ctx *ctx);
 
+/* ---- intermediate stages (debugging) ------------------------------------- */
+
+/*
+ * With debug on (gpolylla_ctx_set_debug), every meshing run of the context
+ * keeps copies of its intermediate stages, so that a mismatch can be traced
+ * to the step that made it: the label bytes and next'/prev' as the relink
+ * left them (Sections 6.1-6.3 and 6.5: before the repair of Section 6.4),
+ * the barrier tips the relink found (half-edges h with next'(h) == twin(h)),
+ * and the label bytes at the end.  Label byte of triangle t: bits 0-1 the
+ * local index of its longest edge, bits 2-4 the frontier bits of its edges
+ * 0-2, bit 5 set when its longest edge is a terminal edge whose seed is in t.
+ * Debug runs do not use captured graphs and cost the copies.
+ */
+int gpolylla_ctx_set_debug(gp_ctx *ctx, int32_t on);
+
+/* Host buffers (each may be NULL) for gpolylla_result_debug. */
+typedef struct {
+    uint8_t *tflag_relink;   /* nt */
+    int32_t *next_relink;    /* 3*nt */
+    int32_t *prev_relink;    /* 3*nt */
+    uint8_t *tflag_final;    /* nt */
+    int32_t *tips;           /* tips_cap: the mesh's barrier tips, in no particular order */
+    int32_t tips_cap;
+    int32_t ntips;           /* out: the mesh's tip count (may exceed tips_cap) */
+} gp_result_debug;
+
+/* Copies a debug run's intermediate stages of one result (waits for the run).
+ * GP_EINVAL when the result did not come from a debug run; the run's own
+ * status otherwise (GP_ECORRUPT still copies, for inspection). */
+int gpolylla_result_debug(gp_result *res, gp_result_debug *out);
+
 /* ---- host-to-host jobs with overlapped copies ---------------------------- */
 
 /*

@@ -70,6 +70,12 @@ class gp_dev_counts(ctypes.Structure):
 GP_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
+class gp_result_debug(ctypes.Structure):
+    _fields_ = [("tflag_relink", ctypes.c_void_p), ("next_relink", ctypes.c_void_p),
+                ("prev_relink", ctypes.c_void_p), ("tflag_final", ctypes.c_void_p), ("tips", ctypes.c_void_p),
+                ("tips_cap", ctypes.c_int32), ("ntips", ctypes.c_int32)]
+
+
 class gp_job(ctypes.Structure):
     _fields_ = [("xy", ctypes.c_void_p), ("nv", ctypes.c_int32), ("tri", ctypes.c_void_p), ("nt", ctypes.c_int32),
                 ("next", ctypes.c_void_p), ("prev", ctypes.c_void_p), ("seeds", ctypes.c_void_p),
@@ -125,6 +131,8 @@ def _load():
         "gpolylla_result_device": (ctypes.c_int, [_P, ctypes.POINTER(gp_result_dev)]),
         "gpolylla_result_free": (None, [_P]),
         "gpolylla_mesh_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(gp_result_dev), _P]),
+        "gpolylla_ctx_set_debug": (ctypes.c_int, [_P, ctypes.c_int32]),
+        "gpolylla_result_debug": (ctypes.c_int, [_P, ctypes.POINTER(gp_result_debug)]),
         "gpolylla_mesh_jobs": (ctypes.c_int, [_P, ctypes.POINTER(gp_job), ctypes.c_int32, ctypes.c_int64,
                                               ctypes.c_uint32]),
         "gpolylla_serve_start": (ctypes.c_int, [_P, ctypes.POINTER(gp_serve_opts), ctypes.POINTER(_P)]),
@@ -161,6 +169,7 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
             "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_mesh_jobs",
+            "gpolylla_ctx_set_debug", "gpolylla_result_debug",
             "gpolylla_serve_start", "gpolylla_serve_submit", "gpolylla_serve_submit_at",
             "gpolylla_serve_wait", "gpolylla_serve_stats", "gpolylla_serve_reset_stats", "gpolylla_serve_stop"]
 
@@ -408,6 +417,23 @@ class Mesh:
             pass
 
 
+def gpolylla_result_debug(res, nt: int) -> dict:
+    """A debug run's intermediate stages of one result, as numpy arrays."""
+    out = {"tflag_relink": np.zeros(max(nt, 1), np.uint8), "tflag_final": np.zeros(max(nt, 1), np.uint8),
+           "next_relink": np.zeros(max(3 * nt, 1), np.int32), "prev_relink": np.zeros(max(3 * nt, 1), np.int32),
+           "tips": np.zeros(max(nt, 1), np.int32)}
+    d = gp_result_debug(*[out[k].ctypes.data for k in ("tflag_relink", "next_relink", "prev_relink",
+                                                        "tflag_final", "tips")], len(out["tips"]), 0)
+    _check(_load().gpolylla_result_debug(res, ctypes.byref(d)), "gpolylla_result_debug")
+    for k in ("tflag_relink", "tflag_final"):
+        out[k] = out[k][:nt]
+    for k in ("next_relink", "prev_relink"):
+        out[k] = out[k][:3 * nt]
+    out["tips"] = np.sort(out["tips"][:min(d.ntips, len(out["tips"]))])
+    out["ntips"] = d.ntips
+    return out
+
+
 class Result:
     def __init__(self, ctx: "Context", handle):
         self.ctx, self.handle = ctx, handle
@@ -417,6 +443,10 @@ class Result:
 
     def copy(self) -> dict:
         return gpolylla_result_copy(self.handle)
+
+    def debug(self) -> dict:
+        """Intermediate stages (a run of a context with debug on)."""
+        return gpolylla_result_debug(self.handle, self.info()["nt"])
 
     def device(self) -> dict:
         return gpolylla_result_device(self.handle)
@@ -495,6 +525,9 @@ class Context:
 
     def kernel_reset(self):
         gpolylla_ctx_kernel_reset(self.handle)
+
+    def set_debug(self, on: bool = True):
+        _check(_load().gpolylla_ctx_set_debug(self.handle, int(on)), "gpolylla_ctx_set_debug")
 
     def set_launch(self, spec: str):
         gpolylla_ctx_set_launch(self.handle, spec)

@@ -54,6 +54,44 @@ void profile_hook(void *user, int kernel, int after) {
     }
 }
 
+// The launch hook of a debug run: after k_relink the label bytes, next',
+// prev' and the tip list are copied aside (in stream order, so before the
+// repair changes them); after the last kernel the label bytes again.
+struct DebugHook {
+    gp_ctx *c;
+    DebugSnap *d;
+    const gp::RunBuffers *rb;
+    std::vector<gp_result *> *res;
+    const std::vector<uint8_t *> *tflag;
+};
+
+void debug_hook(void *user, int kernel, int after) {
+    DebugHook *h = static_cast<DebugHook *>(user);
+    if (h->c->profile) profile_hook(h->c, kernel, after);
+    if (!after) return;
+    hipStream_t s = h->c->stream;
+    const int n = (int)h->res->size();
+    if (kernel == gp::K_RELINK) {
+        for (int i = 0; i < n; i++) {
+            const gp_result *x = (*h->res)[i];
+            const size_t nt = (size_t)x->nt, nh = 3 * nt;
+            if (nt) (void)hipMemcpyAsync(h->d->tflag_relink[i], (*h->tflag)[i], nt, hipMemcpyDeviceToDevice, s);
+            if (nh) {
+                (void)hipMemcpyAsync(h->d->next_relink[i], x->next_o, 4 * nh, hipMemcpyDeviceToDevice, s);
+                (void)hipMemcpyAsync(h->d->prev_relink[i], x->prev_o, 4 * nh, hipMemcpyDeviceToDevice, s);
+            }
+        }
+        (void)hipMemcpyAsync(h->d->tips, h->rb->tips, sizeof(gp::ListEntry) * (size_t)h->d->cap_tips,
+                             hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(h->d->ntips, &h->rb->rc->ntips, sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    } else if (kernel == gp::K_EMIT) {
+        for (int i = 0; i < n; i++) {
+            const size_t nt = (size_t)(*h->res)[i]->nt;
+            if (nt) (void)hipMemcpyAsync(h->d->tflag_final[i], (*h->tflag)[i], nt, hipMemcpyDeviceToDevice, s);
+        }
+    }
+}
+
 // Folds finished event pairs into the per-kernel totals; pairs whose work is
 // still queued stay pending.
 void resolve_profile(gp_ctx *c) {
@@ -135,6 +173,7 @@ hipError_t stage_to_device(gp_ctx *c, void *dst, const void *src, size_t n) {
 
 void run_destroy(RunState *r) {
     pinned_give(r->ctx, r->host_ctrs, r->host_ctrs_bytes);
+    delete r->dbg;
     if (r->done) (void)hipEventDestroy(r->done);
     delete r;
 }
@@ -180,6 +219,10 @@ void run_unref(RunState *r) {
     DeviceGuard g(c->device);
     c->pool.release(r->out_block);
     r->out_block = nullptr;
+    if (r->dbg) {
+        c->pool.release(r->dbg->block);
+        r->dbg->block = nullptr;
+    }
     if (r->synced || hipEventQuery(r->done) == hipSuccess) {
         run_destroy(r);
     } else {
@@ -867,6 +910,41 @@ int gpolylla_ctx_kernel_ms(gp_ctx *c, const char **names, double *avg_ms, int64_
     return n;
 }
 
+int gpolylla_ctx_set_debug(gp_ctx *c, int32_t on) {
+    if (!c) return GP_EINVAL;
+    c->debug = on != 0;
+    return GP_OK;
+}
+
+int gpolylla_result_debug(gp_result *x, gp_result_debug *out) {
+    if (!x || !out || !x->run || x->host) return GP_EINVAL;
+    RunState *r = x->run;
+    if (!r->dbg) return GP_EINVAL;   // not a debug run
+    const int st = run_sync(r);
+    if (st != GP_OK && st != GP_ECORRUPT) return st;
+    DeviceGuard g(r->ctx->device);
+    const DebugSnap &d = *r->dbg;
+    const int i = x->index;
+    const size_t nt = (size_t)x->nt, nh = 3 * nt;
+    if (nt && out->tflag_relink) HIP_OK(hipMemcpy(out->tflag_relink, d.tflag_relink[i], nt, hipMemcpyDeviceToHost));
+    if (nt && out->tflag_final) HIP_OK(hipMemcpy(out->tflag_final, d.tflag_final[i], nt, hipMemcpyDeviceToHost));
+    if (nh && out->next_relink) HIP_OK(hipMemcpy(out->next_relink, d.next_relink[i], 4 * nh, hipMemcpyDeviceToHost));
+    if (nh && out->prev_relink) HIP_OK(hipMemcpy(out->prev_relink, d.prev_relink[i], 4 * nh, hipMemcpyDeviceToHost));
+    int32_t total = 0;
+    HIP_OK(hipMemcpy(&total, d.ntips, sizeof total, hipMemcpyDeviceToHost));
+    total = std::max(0, std::min(total, d.cap_tips));
+    std::vector<gp::ListEntry> all((size_t)total);
+    if (total) HIP_OK(hipMemcpy(all.data(), d.tips, sizeof(gp::ListEntry) * (size_t)total, hipMemcpyDeviceToHost));
+    int32_t k = 0;
+    for (const gp::ListEntry &e : all) {
+        if (e.mesh != i) continue;
+        if (out->tips && k < out->tips_cap) out->tips[k] = e.he;
+        k++;
+    }
+    out->ntips = k;
+    return st;
+}
+
 void gpolylla_ctx_kernel_reset(gp_ctx *c) {
     if (!c) return;
     for (int k = 0; k < gp::K_COUNT; k++) {
@@ -994,7 +1072,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     reap_retired(c, false);
 
     // scratch: per call from the pool, or owned by a cached graph
-    const bool use_graph = (out_flags & GP_GRAPH) && !c->profile;
+    const bool use_graph = (out_flags & GP_GRAPH) && !c->profile && !c->debug;
     GraphEntry *ge = nullptr;
     void *p_tmp = nullptr;
     if (use_graph) {
@@ -1091,9 +1169,37 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         else if (ge)
             ge->staged = descs;
     }
+    DebugHook dh{c, nullptr, &rb, &res, &tflag};
+    if (err == GP_OK && c->debug) {
+        // the snapshots' memory: per mesh two label arrays and next', prev'
+        DebugSnap *d = new (std::nothrow) DebugSnap();
+        size_t bytes = align_up(sizeof(gp::ListEntry) * (size_t)std::max(rb.cap_tips, 1)) + kAlign;
+        for (int i = 0; i < n; i++)
+            bytes += 2 * align_up((size_t)std::max(res[i]->nt, 1)) +
+                     2 * align_up(sizeof(int32_t) * 3 * (size_t)std::max(res[i]->nt, 1));
+        if (!d || c->pool.alloc(bytes, &d->block) != GP_OK) {
+            delete d;
+            err = GP_ENOMEM;
+        } else {
+            Arena ad{static_cast<char *>(d->block), bytes, 0};
+            d->cap_tips = rb.cap_tips;
+            d->tips = ad.take<gp::ListEntry>((size_t)std::max(rb.cap_tips, 1));
+            d->ntips = ad.take<int32_t>(1);
+            for (int i = 0; i < n; i++) {
+                const size_t nt = (size_t)std::max(res[i]->nt, 1);
+                d->tflag_relink.push_back(ad.take<uint8_t>(nt));
+                d->tflag_final.push_back(ad.take<uint8_t>(nt));
+                d->next_relink.push_back(ad.take<int32_t>(3 * nt));
+                d->prev_relink.push_back(ad.take<int32_t>(3 * nt));
+            }
+            r->dbg = d;
+            dh.d = d;
+        }
+    }
     if (err == GP_OK) {
         hipError_t e = ge ? hipGraphLaunch(ge->exec, s)
-                          : gp::launch_pipeline(c->cfg, rb, s, c->profile ? profile_hook : nullptr, c);
+                          : c->debug ? gp::launch_pipeline(c->cfg, rb, s, debug_hook, &dh)
+                                     : gp::launch_pipeline(c->cfg, rb, s, c->profile ? profile_hook : nullptr, c);
         if (e != hipSuccess) err = GP_EHIP;
     }
     if (err == GP_OK && (gp::launch_copy_words(r->host_ctrs, rb.ctrs, sizeof(gp::MeshCounters) * n, s) !=
@@ -1108,6 +1214,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         (void)hipStreamSynchronize(s);
         for (auto q : res) delete q;
         c->pool.release(r->out_block);
+        if (r->dbg) c->pool.release(r->dbg->block);
         run_destroy(r);
         return err;
     }

@@ -172,6 +172,7 @@ struct gp_ctx {
     gprt::DevPool pool;
     gp::LaunchCfg cfg;
     bool profile = false;
+    bool debug = false;   // runs keep snapshots of their intermediate stages
     struct Pending {
         int kernel;
         hipEvent_t a, b;
@@ -224,9 +225,22 @@ inline void mesh_desc_fill(const gp_mesh *m, gp::MeshDesc &d) {
 }
 
 namespace gprt {
+// Snapshots of a debug run's intermediate stages (device memory): per mesh
+// the label bytes and next'/prev' as k_relink left them (before the repair),
+// and the label bytes at the end; for the run, the barrier-tip list.
+struct DebugSnap {
+    void *block = nullptr;
+    std::vector<uint8_t *> tflag_relink, tflag_final;
+    std::vector<int32_t *> next_relink, prev_relink;
+    gp::ListEntry *tips = nullptr;    // cap_tips entries
+    int32_t *ntips = nullptr;         // the run's tip count
+    int32_t cap_tips = 0;
+};
+
 struct RunState {
     gp_ctx *ctx = nullptr;
     void *out_block = nullptr;        // outputs of every mesh of the run
+    DebugSnap *dbg = nullptr;         // debug runs only
     gp::MeshCounters *host_ctrs = nullptr;  // pinned
     size_t host_ctrs_bytes = 0;
     int nmesh = 0;

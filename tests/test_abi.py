@@ -68,7 +68,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     (size and every field offset), checked with the host compiler."""
     import subprocess
     import paper_2403_14723_amd as gp
-    structs = {"gp_job": gp.gp_job, "gp_result_dev": gp.gp_result_dev, "gp_dev_counts": gp.gp_dev_counts}
+    structs = {"gp_job": gp.gp_job, "gp_result_dev": gp.gp_result_dev, "gp_dev_counts": gp.gp_dev_counts,
+               "gp_result_debug": gp.gp_result_debug}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
