@@ -306,7 +306,11 @@ def _graph_form(gp, stream, m, steps, bflags=0):
     times from a profiled pass."""
     import torch
     ctx = gp.Context(0, stream=stream.cuda_stream)
+    ctx.build_halfedges(m.xy, m.tri, bflags).free()   # the pool's first allocation untimed
+    torch.cuda.synchronize()
+    b0 = time.perf_counter()
     h = ctx.build_halfedges(m.xy, m.tri, bflags)
+    build_ms = (time.perf_counter() - b0) * 1e3
     mesh_bytes, escapes = h.nbytes()
     flags = gp.GP_ASYNC | gp.GP_GRAPH
     for _ in range(3):
@@ -337,7 +341,7 @@ def _graph_form(gp, stream, m, steps, bflags=0):
             "loop_half_edges": info["nloop_he"], "tips": info["ntips"], "ms_per_step": round(ms, 4),
             "mtri_s": round(m.nt / (ms * 1e-3) / 1e6, 1), "kernels_ms": kms,
             "mesh_bytes": mesh_bytes, "mesh_bytes_per_triangle": round(mesh_bytes / max(m.nt, 1), 2),
-            "escapes": escapes}
+            "escapes": escapes, "build_ms_host_to_mesh": round(build_ms, 3)}
 
 
 def bench_compact(gp, stream, mesh, steps):
@@ -357,12 +361,21 @@ def bench_compact(gp, stream, mesh, steps):
 def bench_delaunay(gp, W, stream, steps, npts=1_000_000):
     """The general-position workload (the paper's Random meshes): a Delaunay
     triangulation of random points, numbered along a Z-order curve, meshed on
-    the device like the plain workload (graph replay)."""
+    the device like the plain workload (graph replay); the same points in
+    Qhull's output order, as given and renumbered by the build."""
     t0 = time.perf_counter()
     m = W.delaunay_1m() if npts == 1_000_000 else W.random_delaunay(npts, seed=21, order="morton")
     gen_s = time.perf_counter() - t0
     out = _graph_form(gp, stream, m, steps)
     out["generate_s"] = round(gen_s, 1)
+    # the same points in the triangulator's own order, as given and renumbered
+    # by the build (GP_RENUMBER: the mesh and its results in the new numbering)
+    q = W.random_delaunay(npts, seed=21, order="qhull")
+    keep = ("ms_per_step", "mtri_s", "kernels_ms", "build_ms_host_to_mesh")
+    r = _graph_form(gp, stream, q, steps)
+    out["qhull_order"] = {k: r[k] for k in keep}
+    r = _graph_form(gp, stream, q, steps, gp.GP_RENUMBER)
+    out["qhull_order_renumbered"] = {k: r[k] for k in keep}
     return out
 
 

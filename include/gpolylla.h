@@ -65,6 +65,7 @@ extern "C" {
 /* ---- flags -------------------------------------------------------------- */
 #define GP_IN_DEVICE 0x1u     /* build: xy and tri are device pointers on the context's device */
 #define GP_COMPACT 0x8u       /* build: keep the mesh in the compact encoding (gpolylla_build_halfedges) */
+#define GP_RENUMBER 0x40u     /* build: renumber along a Z-order curve first (gpolylla_build_halfedges) */
 #define GP_ASYNC 0x2u         /* mesh: return once the work is queued; counts are read
                                  (and errors reported) by the first result query */
 #define GP_GRAPH 0x4u         /* mesh: replay a captured hipGraph of the kernel chain; the
@@ -162,6 +163,15 @@ int gpolylla_ctx_get_launch(const gp_ctx *ctx, char *buf, int32_t cap);
  * whose offsets do not fit in a hash table.  About 14 bytes per triangle
  * instead of 24 (xy unchanged); every meshing call gives the same results
  * as with the int32 arrays.
+ * GP_RENUMBER first renumbers the input on the device, vertices in the
+ * Z-order (Morton) order of their coordinates and triangles in that of their
+ * centroids (corners keep their order within a triangle), which restores the
+ * locality the kernels need to input numbered without it.  The mesh, and
+ * every result of meshing it, are then in the new numbering, exactly as if
+ * the caller had passed the renumbered input; gpolylla_mesh_permutation
+ * gives the maps back to the caller's numbering.  Ties between equal edge
+ * lengths are broken by edge id (Section 2 reading), so they may fall
+ * differently than in the original numbering.
  */
 int gpolylla_build_halfedges(gp_ctx *ctx, const int32_t *xy, int32_t nv, const int32_t *tri,
                              int32_t nt, uint32_t flags, gp_mesh **out);
@@ -170,6 +180,10 @@ int gpolylla_build_halfedges(gp_ctx *ctx, const int32_t *xy, int32_t nv, const i
  * receives the re-oriented count. */
 int gpolylla_mesh_copy(const gp_mesh *mesh, int32_t *org, int32_t *twin, int64_t *nflipped);
 int gpolylla_mesh_size(const gp_mesh *mesh, int32_t *nv, int32_t *nt);
+/* The maps of a renumbered mesh (GP_RENUMBER) back to the caller's
+ * numbering: tri_new_to_old (nt) and vert_new_to_old (nv), host buffers,
+ * either may be NULL.  GP_EINVAL for a mesh built without GP_RENUMBER. */
+int gpolylla_mesh_permutation(const gp_mesh *mesh, int32_t *tri_new_to_old, int32_t *vert_new_to_old);
 /* Device bytes the mesh holds (coordinates, corners, twins; in a compact
  * mesh the escape table too); escapes (may be NULL) receives the number of
  * escaped values of a compact mesh (0 otherwise). */

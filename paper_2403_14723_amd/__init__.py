@@ -24,6 +24,7 @@ GP_EINVAL, GP_ERANGE, GP_EDEGEN, GP_ENONMANIFOLD, GP_ENOMEM, GP_EHIP = -1, -2, -
 GP_EAGAIN, GP_ETOOBIG, GP_ETIMEDOUT, GP_ECORRUPT = -7, -8, -9, -10
 GP_IN_DEVICE = 0x1
 GP_COMPACT = 0x8
+GP_RENUMBER = 0x40
 GP_ASYNC = 0x2
 GP_GRAPH = 0x4
 GP_OUT_LOOPS = 0x10
@@ -122,6 +123,7 @@ def _load():
         "gpolylla_mesh_copy": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
         "gpolylla_mesh_size": (ctypes.c_int, [_P, _I32P, _I32P]),
         "gpolylla_mesh_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64)]),
+        "gpolylla_mesh_permutation": (ctypes.c_int, [_P, _P, _P]),
         "gpolylla_mesh_free": (None, [_P]),
         "gpolylla_mesh": (ctypes.c_int, [_P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
         "gpolylla_mesh_batch": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_uint32,
@@ -166,6 +168,7 @@ _SYMBOLS = ["gpolylla_strerror", "gpolylla_ctx_create", "gpolylla_ctx_destroy", 
             "gpolylla_ctx_sync", "gpolylla_ctx_kernel_ms", "gpolylla_ctx_kernel_reset",
             "gpolylla_ctx_set_launch", "gpolylla_ctx_get_launch",
             "gpolylla_build_halfedges", "gpolylla_mesh_copy", "gpolylla_mesh_size", "gpolylla_mesh_bytes",
+            "gpolylla_mesh_permutation",
             "gpolylla_mesh_free",
             "gpolylla_mesh", "gpolylla_mesh_batch", "gpolylla_result_info", "gpolylla_result_copy",
             "gpolylla_result_device", "gpolylla_result_free", "gpolylla_mesh_noalloc", "gpolylla_mesh_jobs",
@@ -397,6 +400,16 @@ class Mesh:
 
     def copy(self):
         return gpolylla_mesh_copy(self.handle)
+
+    def permutation(self) -> tuple:
+        """(triangle new -> old, vertex new -> old) of a renumbered mesh"""
+        nv, nt = ctypes.c_int32(), ctypes.c_int32()
+        _check(_load().gpolylla_mesh_size(self.handle, ctypes.byref(nv), ctypes.byref(nt)), "gpolylla_mesh_size")
+        tp = np.empty(max(nt.value, 1), np.int32)
+        vp = np.empty(max(nv.value, 1), np.int32)
+        _check(_load().gpolylla_mesh_permutation(self.handle, tp.ctypes.data, vp.ctypes.data),
+               "gpolylla_mesh_permutation")
+        return tp[:nt.value], vp[:nv.value]
 
     def nbytes(self) -> tuple[int, int]:
         """(device bytes the mesh holds, escaped values of a compact mesh)"""

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpolylla.so")
-SOURCES = ["mesh_kernels.hip", "build_kernels.hip", "runtime.cpp", "serve.cpp", "jobs.cpp"]
+SOURCES = ["mesh_kernels.hip", "build_kernels.hip", "renumber.hip", "runtime.cpp", "serve.cpp", "jobs.cpp"]
 ARCH = os.environ.get("GPOLYLLA_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

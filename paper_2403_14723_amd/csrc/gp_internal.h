@@ -192,6 +192,27 @@ hipError_t launch_build_orient(const BuildBuffers &b, hipStream_t s);
 hipError_t launch_build_link(const BuildBuffers &b, hipStream_t s);
 int32_t build_scan_tiles(int32_t n);
 
+// ---- renumbering along a Z-order curve (renumber.hip) ---------------------
+
+struct RenumberBuffers {
+    const int2 *xy_in;
+    const int32_t *tri_in;
+    int32_t nv, nt;
+    int2 *xy_out;          // nv, in the new vertex order
+    int32_t *tri_out;      // 3 nt, new triangle order, new vertex indices
+    int32_t *vperm;        // nv: new -> old vertex
+    int32_t *tperm;        // nt: new -> old triangle
+    int32_t *vinv;         // nv: old -> new vertex (scratch)
+    uint64_t *keys, *keys_alt;   // max(nv, nt) each (scratch)
+    int32_t *vals;               // max(nv, nt) (scratch)
+    void *sort_tmp;              // sort_bytes (scratch)
+    size_t sort_bytes;
+};
+
+// scratch bytes of the radix sort of n key-value pairs
+size_t renumber_sort_bytes(int32_t n);
+hipError_t launch_renumber(const RenumberBuffers &b, hipStream_t s);
+
 // ---- compact half-edge encoding (build_kernels.hip) ----------------------
 //
 // A compact mesh keeps its corners and twins in 16-bit offsets: the twin of

@@ -533,6 +533,76 @@ int compact_mesh(gp_ctx *c, gp_mesh *m, int32_t *host) {
     return GP_OK;
 }
 
+// The renumbered copy of one build's input (GP_RENUMBER): device arrays in
+// the new numbering, the two maps, and the scratch they took.
+struct Renumbered {
+    void *xy = nullptr, *tri = nullptr, *vperm = nullptr, *tperm = nullptr, *tmp = nullptr;
+    void *in_xy = nullptr, *in_tri = nullptr;   // uploads of host inputs
+};
+
+void renumbered_free(gp_ctx *c, Renumbered &r, bool keep_maps) {
+    for (void *p : {r.xy, r.tri, r.tmp, r.in_xy, r.in_tri}) c->pool.release(p);
+    if (!keep_maps) {
+        c->pool.release(r.vperm);
+        c->pool.release(r.tperm);
+    }
+    r = Renumbered{};
+}
+
+// Queues the renumbering of one input on the context's stream.
+int renumber_input(gp_ctx *c, const int32_t *xy, int32_t nv, const int32_t *tri, int32_t nt, bool in_dev,
+                   Renumbered &r) {
+    if (nv < 0 || nt < 0 || (nv > 0 && !xy) || (nt > 0 && !tri)) return GP_EINVAL;
+    if (3ll * nt >= (1ll << 31)) return GP_ERANGE;
+    hipStream_t s = c->stream;
+    const size_t nxy = sizeof(int2) * (size_t)std::max(nv, 1), ntri = 12 * (size_t)std::max(nt, 1);
+    const int32_t nmax = std::max(std::max(nv, nt), 1);
+    const size_t sort = gp::renumber_sort_bytes(nmax);
+    if (!sort) return GP_EHIP;
+    int rc = c->pool.alloc(nxy, &r.xy);
+    if (rc == GP_OK) rc = c->pool.alloc(ntri, &r.tri);
+    if (rc == GP_OK) rc = c->pool.alloc(4 * (size_t)std::max(nv, 1), &r.vperm);
+    if (rc == GP_OK) rc = c->pool.alloc(4 * (size_t)std::max(nt, 1), &r.tperm);
+    const size_t tmp = arena_bytes<int32_t>(nmax) * 2 + arena_bytes<uint64_t>(nmax) * 2 + align_up(sort);
+    if (rc == GP_OK) rc = c->pool.alloc(tmp, &r.tmp);
+    const void *src_xy = xy, *src_tri = tri;
+    if (rc == GP_OK && !in_dev) {   // the inputs are read several times: upload them once
+        rc = c->pool.alloc(nxy, &r.in_xy);
+        if (rc == GP_OK) rc = c->pool.alloc(ntri, &r.in_tri);
+        if (rc == GP_OK &&
+            ((nv > 0 && hipMemcpyAsync(r.in_xy, xy, sizeof(int2) * (size_t)nv, hipMemcpyHostToDevice, s) != hipSuccess) ||
+             (nt > 0 && hipMemcpyAsync(r.in_tri, tri, 12 * (size_t)nt, hipMemcpyHostToDevice, s) != hipSuccess)))
+            rc = GP_EHIP;
+        src_xy = r.in_xy;
+        src_tri = r.in_tri;
+    }
+    if (rc != GP_OK) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    Arena a{static_cast<char *>(r.tmp), tmp, 0};
+    gp::RenumberBuffers b{};
+    b.xy_in = static_cast<const int2 *>(src_xy);
+    b.tri_in = static_cast<const int32_t *>(src_tri);
+    b.nv = nv;
+    b.nt = nt;
+    b.xy_out = static_cast<int2 *>(r.xy);
+    b.tri_out = static_cast<int32_t *>(r.tri);
+    b.vperm = static_cast<int32_t *>(r.vperm);
+    b.tperm = static_cast<int32_t *>(r.tperm);
+    b.vinv = a.take<int32_t>(nmax);
+    b.vals = a.take<int32_t>(nmax);
+    b.keys = a.take<uint64_t>(nmax);
+    b.keys_alt = a.take<uint64_t>(nmax);
+    b.sort_tmp = a.take<char>(sort);
+    b.sort_bytes = sort;
+    if (gp::launch_renumber(b, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return GP_EHIP;
+    }
+    return GP_OK;
+}
+
 }  // namespace
 
 int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
@@ -553,7 +623,19 @@ int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, co
                 if (j.rc == GP_OK) j.rc = GP_EHIP;
         }
     };
-    for (int i = 0; i < n; i++) jobs[i].rc = build_stage0(c, xy[i], nv[i], tri[i], nt[i], flags, jobs[i]);
+    // renumbered inputs (GP_RENUMBER): built from their device copies
+    std::vector<Renumbered> rn((flags & GP_RENUMBER) ? n : 0);
+    for (int i = 0; i < n; i++) {
+        if (flags & GP_RENUMBER) {
+            jobs[i].rc = renumber_input(c, xy[i], nv[i], tri[i], nt[i], (flags & GP_IN_DEVICE) != 0, rn[i]);
+            if (jobs[i].rc == GP_OK)
+                jobs[i].rc = build_stage0(c, static_cast<const int32_t *>(rn[i].xy), nv[i],
+                                          static_cast<const int32_t *>(rn[i].tri), nt[i], flags | GP_IN_DEVICE,
+                                          jobs[i]);
+        } else {
+            jobs[i].rc = build_stage0(c, xy[i], nv[i], tri[i], nt[i], flags, jobs[i]);
+        }
+    }
     drain();
     for (BuildJob &j : jobs)
         if (j.rc == GP_OK) j.rc = build_stage1(c, j);
@@ -564,6 +646,7 @@ int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, co
         for (BuildJob &j : jobs)
             if (j.rc == GP_OK) j.rc = compact_mesh(c, j.m, j.nflip_h);
     // a failed job's memory goes back after the stream has drained its work
+    // (as do the renumbered inputs, which the builds have finished reading)
     bool failed = false;
     for (BuildJob &j : jobs) failed |= j.rc != GP_OK;
     if (failed) drain();
@@ -571,8 +654,15 @@ int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, co
         status[i] = jobs[i].rc;
         if (jobs[i].rc == GP_OK) {
             out[i] = jobs[i].m;
+            if (!rn.empty()) {
+                out[i]->vperm = static_cast<int32_t *>(rn[i].vperm);
+                out[i]->tperm = static_cast<int32_t *>(rn[i].tperm);
+                out[i]->bytes += align_up(4 * (size_t)std::max(nv[i], 1)) + align_up(4 * (size_t)std::max(nt[i], 1));
+                renumbered_free(c, rn[i], true);
+            }
         } else {
             build_abort(c, jobs[i]);
+            if (!rn.empty()) renumbered_free(c, rn[i], false);
         }
     }
     pinned_give(c, host, hb);
@@ -1026,6 +1116,16 @@ int gpolylla_mesh_copy(const gp_mesh *m, int32_t *org, int32_t *twin, int64_t *n
     return rc;
 }
 
+int gpolylla_mesh_permutation(const gp_mesh *m, int32_t *tri_new_to_old, int32_t *vert_new_to_old) {
+    if (!m || !m->tperm) return GP_EINVAL;
+    DeviceGuard g(m->ctx->device);
+    if (tri_new_to_old && m->nt)
+        HIP_OK(hipMemcpy(tri_new_to_old, m->tperm, 4 * (size_t)m->nt, hipMemcpyDeviceToHost));
+    if (vert_new_to_old && m->nv)
+        HIP_OK(hipMemcpy(vert_new_to_old, m->vperm, 4 * (size_t)m->nv, hipMemcpyDeviceToHost));
+    return GP_OK;
+}
+
 int gpolylla_mesh_bytes(const gp_mesh *m, size_t *bytes, int64_t *escapes) {
     if (!m) return GP_EINVAL;
     if (bytes) *bytes = m->bytes;
@@ -1050,6 +1150,8 @@ void gpolylla_mesh_free(gp_mesh *m) {
     m->ctx->pool.release(m->org8);
     m->ctx->pool.release(m->twin16);
     m->ctx->pool.release(m->esc);
+    m->ctx->pool.release(m->vperm);
+    m->ctx->pool.release(m->tperm);
     delete m;
 }
 

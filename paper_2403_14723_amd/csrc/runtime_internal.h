@@ -210,6 +210,9 @@ struct gp_mesh {
     int32_t *esc = nullptr;
     int32_t esc_mask = 0;
     int32_t nesc = 0;
+    // renumbered meshes (GP_RENUMBER): new -> old vertex and triangle index
+    int32_t *vperm = nullptr;
+    int32_t *tperm = nullptr;
     size_t bytes = 0;          // device bytes the mesh holds
 };
 
