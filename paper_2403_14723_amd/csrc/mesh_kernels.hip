@@ -1242,7 +1242,23 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
     }
 }
 
-// The loops k_compact left out: each written from its minimum at its offset.
+// Length of the loop starting at mn (when it did not fit in the byte).
+__device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
+    const gcint nx = (gcint)d.next_o;
+    const int nh = 3 * d.nt;
+    int cur = mn, len = 0;
+    do {
+        ++len;
+        cur = nx[cur];
+        if (cur < 0 || len > nh) return -1;
+    } while (cur != mn);
+    return len;
+}
+
+// The loops k_compact left out, each written from its minimum at its offset
+// from both ends at once: position s forward along next' and position len - s
+// backward along prev', so the two loads of a step are in flight together and
+// a loop of len half-edges takes about len / 2 dependent steps.
 template <int ITEMS>
 __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs, const EmitEntry *emit,
                                               const int32_t *emit_counts, int emit_cap) {
@@ -1250,49 +1266,58 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
     const int total = striped_prefix(emit_counts, emit_cap, s_pref);
     const int nthreads = gridDim.x * blockDim.x;
     for (int g0 = blockIdx.x * blockDim.x + threadIdx.x; g0 < total; g0 += nthreads * ITEMS) {
-        gcint nx[ITEMS];
+        gcint nx[ITEMS], pv[ITEMS];
         gint out[ITEMS];
-        int mesh[ITEMS], cur[ITEMS], mn[ITEMS], pos[ITEMS], lim[ITEMS];
+        int mesh[ITEMS], f[ITEMS], b[ITEMS], len[ITEMS];
+        bool live[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            cur[j] = -1;
-            mesh[j] = mn[j] = pos[j] = lim[j] = 0;
-            nx[j] = nullptr;
+            live[j] = false;
+            f[j] = b[j] = len[j] = mesh[j] = 0;
+            nx[j] = pv[j] = nullptr;
             out[j] = nullptr;
             const int g = g0 + j * nthreads;
             if (g >= total) continue;
             const EmitEntry e = emit[striped_index(s_pref, emit_cap, g)];
             const MeshDesc &d = descs[e.mesh];
             mesh[j] = e.mesh;
+            // k_compact left the loop's length in its first slot
+            const int L = (e.off >= 0 && e.off < 3 * d.nt) ? ((gcint)d.loop_he)[e.off] : -1;
+            if (L < 1 || (long long)e.off + L > 3ll * d.nt) {
+                atomicOr(&d.ctr->err, kErrCorrupt);
+                continue;
+            }
             nx[j] = (gcint)d.next_o;
-            out[j] = (gint)d.loop_he;
-            cur[j] = mn[j] = e.mn;
-            pos[j] = e.off;
-            lim[j] = 3 * d.nt;
+            pv[j] = (gcint)d.prev_o;
+            out[j] = (gint)d.loop_he + e.off;
+            f[j] = b[j] = e.mn;
+            len[j] = L;
+            out[j][0] = e.mn;
+            live[j] = L > 1;
         }
-        bool active = true;
-        while (active) {
-            active = false;
+        for (int s = 1;; s++) {
+            bool active = false;
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
-                if (cur[j] < 0) continue;
-                if (pos[j] >= lim[j]) {
+                if (!live[j]) continue;
+                const int bi = len[j] - s;   // the backward end's position; the forward end's is s
+                if (s > bi) {
+                    live[j] = false;
+                    continue;
+                }
+                const int nf = nx[j][f[j]], nb = pv[j][b[j]];   // both in flight together
+                if (nf < 0 || nb < 0) {
                     atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
-                    cur[j] = -1;
+                    live[j] = false;
                     continue;
                 }
-                out[j][pos[j]++] = cur[j];
-                cur[j] = nx[j][cur[j]];
-                if (cur[j] < 0) {
-                    atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
-                    continue;
-                }
-                if (cur[j] == mn[j]) {
-                    cur[j] = -1;
-                    continue;
-                }
+                out[j][s] = nf;
+                if (s < bi) out[j][bi] = nb;
+                f[j] = nf;
+                b[j] = nb;
                 active = true;
             }
+            if (!active) break;
         }
     }
 }
@@ -1361,18 +1386,6 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__
 // prefix; each tile assembles its part in LDS and writes it contiguously
 // ---------------------------------------------------------------------------
 
-// Length of the loop starting at mn (when it did not fit in the byte).
-__device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
-    const gcint nx = (gcint)d.next_o;
-    const int nh = 3 * d.nt;
-    int cur = mn, len = 0;
-    do {
-        ++len;
-        cur = nx[cur];
-        if (cur < 0 || len > nh) return -1;
-    } while (cur != mn);
-    return len;
-}
 
 template <int ITEMS>
 __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ descs, int nmesh,
@@ -1556,6 +1569,9 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
                     emit[e].mn = mn;
                     emit[e].off = ps + off;
                 }
+                // the loop's length in its own first slot, which k_emit reads
+                // and then overwrites with the minimum
+                he_out[off] = lens[j];
                 ++e;
             }
         }
