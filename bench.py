@@ -391,11 +391,12 @@ def bench_band(gp, W, stream, mesh, steps, nbands=8, band=3):
     return out
 
 
-def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lanes=4):
+def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lanes=4, loops_only=False):
     """Continuous-batching server: capacity from a closed loop, then Poisson
     arrivals at rho * capacity; latency = scheduled arrival -> result on the
-    host (the server stamps each request with its arrival time).  The
-    warm-up closed loop is as large as the capacity run, so that the server's
+    host (the server stamps each request with its arrival time).  loops_only:
+    results carry seeds and loops, not next'/prev' (a third of the download).
+    The warm-up closed loop is as large as the capacity run, so that the server's
     input pool already holds a buffer for every request in flight (a steady
     state server's pool does)."""
     import queue
@@ -404,7 +405,7 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lane
     reqs = W.served_requests(n_req)
     mean_t = float(np.mean([m.nt for m in reqs]))
     ctx = gp.Context(0)
-    srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=n_lanes)
+    srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=n_lanes, loops_only=loops_only)
 
     def closed_loop(n):
         ts = [srv.submit(reqs[i % n_req].xy, reqs[i % n_req].tri) for i in range(n)]
@@ -416,7 +417,8 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lane
     closed_loop(cap_n)
     cap = srv.stats()["mtri_s"]
     out = {"requests": n_req, "mean_triangles": round(mean_t), "distinct_meshes": len({id(m) for m in reqs}),
-           "capacity_mtri_s": round(cap, 1), "lanes": n_lanes, "max_batch": 32, "runs": []}
+           "capacity_mtri_s": round(cap, 1), "lanes": n_lanes, "max_batch": 32,
+           "outputs": "seeds and loops" if loops_only else "next', prev', seeds and loops", "runs": []}
     for k, rho in enumerate(rhos):
         lam = rho * cap * 1e6 / mean_t
         gaps = W.poisson_gaps(n_req, lam, seed=5 + k)
@@ -605,7 +607,7 @@ def main():
         chain_traffic = sum(chain_rec[k.split("<")[0]]["fetch_bytes"] + chain_rec[k.split("<")[0]]["write_bytes"]
                             for k in kms)
 
-    batched = served = delaunay = transfers = band = pipeline = compact = None
+    batched = served = served_loops = delaunay = transfers = band = pipeline = compact = None
     if not args.no_forms:
         log("[bench] one row band of an 8-way split (two halo rows)")
         band = bench_band(gp, W, stream, mesh, max(5, args.steps // 2))
@@ -627,6 +629,9 @@ def main():
         log("[bench] served (Poisson arrivals)")
         served = bench_served(gp, W, n_req=args.served_requests)
         log(f"[bench] {served}")
+        log("[bench] served, loops-only results")
+        served_loops = bench_served(gp, W, n_req=args.served_requests, n_lanes=6, loops_only=True)
+        log(f"[bench] {served_loops}")
 
     cpu = None
     if not args.no_cpu:
@@ -670,6 +675,7 @@ def main():
                      "with_copies_mtri_s": round(nt / ((h2d_ms + build_ms + ms_per_step + d2h_ms) * 1e-3) / 1e6, 2)},
         "batched": batched,
         "served": served,
+        "served_loops_only": served_loops,
         "delaunay": delaunay,
         "band": band,
         "transfers": transfers,

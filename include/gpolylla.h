@@ -97,6 +97,8 @@ typedef struct {
     int64_t nmiddle;      /* distinct middle edges added by the repair */
     int64_t nties;        /* triangles whose largest squared length is shared */
     int64_t nflipped;     /* triangles given clockwise (from the build) */
+    int64_t loops_only;   /* 1: the result holds seeds and loops only (a server
+                             started with loops_only): next'/prev' cannot be copied */
 } gp_result_info;
 
 typedef struct {      /* device views of a result (valid until gpolylla_result_free) */
@@ -216,7 +218,8 @@ int gpolylla_mesh_batch(gp_ctx *ctx, const gp_mesh *const *meshes, int32_t n, ui
 int gpolylla_result_info(gp_result *res, gp_result_info *info);
 /* Copies outputs to caller-allocated host buffers sized from the info
  * (next, prev: nh; seeds: npoly; loop_off: npoly+1; loop_he: nloop_he).
- * NULL skips an output. */
+ * NULL skips an output.  GP_EINVAL when next or prev is asked of a result
+ * that holds loops only (info.loops_only). */
 int gpolylla_result_copy(gp_result *res, int32_t *next, int32_t *prev, int32_t *seeds,
                          int32_t *loop_off, int32_t *loop_he);
 /* Device pointers of the outputs, for zero-copy consumers. */
@@ -350,6 +353,8 @@ typedef struct {
     int32_t max_batch;   /* requests per batched run; 0 = 64 */
     int32_t max_queue;   /* queued requests before GP_EAGAIN; 0 = 4096 */
     int32_t n_lanes;     /* streams whose batches overlap on the device (1..8); 0 = 2 */
+    int32_t loops_only;  /* 1: results hold seeds and loops only, not next'/prev' (a
+                            polygon is given by its loop; the download shrinks to a third) */
 } gp_serve_opts;
 
 typedef struct {
@@ -367,7 +372,9 @@ typedef struct {
  * exact device footprint of the batch (every half-edge build plus the
  * batched meshing run) fits a lane's arena.  Batches on different lanes
  * overlap; requests that arrive while batches run join the next free lane
- * (continuous batching).  ctx itself is not used after the call.
+ * (continuous batching).  With loops_only, only the seeds and loops of each
+ * result are copied back (next'/prev' stay on the device and are dropped).
+ * ctx itself is not used after the call.
  */
 int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out);
 /* Queues a triangulation (host arrays, copied before return).  Errors:

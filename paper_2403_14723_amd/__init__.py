@@ -45,12 +45,12 @@ class gp_ctx_opts(ctypes.Structure):
 
 class gp_result_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("nt", "nv", "nh", "npoly", "nloop_he", "nterminal",
-                                              "ntips", "nmiddle", "nties", "nflipped")]
+                                              "ntips", "nmiddle", "nties", "nflipped", "loops_only")]
 
 
 class gp_serve_opts(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
-                ("max_queue", ctypes.c_int32), ("n_lanes", ctypes.c_int32)]
+                ("max_queue", ctypes.c_int32), ("n_lanes", ctypes.c_int32), ("loops_only", ctypes.c_int32)]
 
 
 class gp_serve_stats(ctypes.Structure):
@@ -313,10 +313,12 @@ def gpolylla_result_info(res) -> dict:
 def gpolylla_result_copy(res) -> dict:
     info = gpolylla_result_info(res)
     nh, p, f = info["nh"], info["npoly"], info["nloop_he"]
-    out = {"next": np.empty(nh, np.int32), "prev": np.empty(nh, np.int32), "seeds": np.empty(p, np.int32),
-           "loop_off": np.empty(p + 1, np.int32), "loop_he": np.empty(f, np.int32)}
+    out = {"seeds": np.empty(p, np.int32), "loop_off": np.empty(p + 1, np.int32), "loop_he": np.empty(f, np.int32)}
+    if not info["loops_only"]:   # a loops-only served result holds no next'/prev'
+        out["next"] = np.empty(nh, np.int32)
+        out["prev"] = np.empty(nh, np.int32)
     ptr = {k: (v.ctypes.data if v.size else None) for k, v in out.items()}
-    _check(_load().gpolylla_result_copy(res, ptr["next"], ptr["prev"], ptr["seeds"], ptr["loop_off"],
+    _check(_load().gpolylla_result_copy(res, ptr.get("next"), ptr.get("prev"), ptr["seeds"], ptr["loop_off"],
                                         ptr["loop_he"]), "gpolylla_result_copy")
     out["info"] = info
     return out
@@ -481,8 +483,10 @@ class Server:
     """Continuous-batching server (see gpolylla_serve_start)."""
 
     def __init__(self, ctx: "Context", pool_bytes: int = 0, max_batch: int = 0, max_queue: int = 0,
-                 n_lanes: int = 0):
-        self.handle = gpolylla_serve_start(ctx.handle, gp_serve_opts(pool_bytes, max_batch, max_queue, n_lanes))
+                 n_lanes: int = 0, loops_only: bool = False):
+        """loops_only: results carry seeds and loops only (no next'/prev')."""
+        self.handle = gpolylla_serve_start(ctx.handle, gp_serve_opts(pool_bytes, max_batch, max_queue, n_lanes,
+                                                                     int(loops_only)))
         self._ctx = ctx
 
     def submit(self, xy, tri, arrival_ns: int = 0) -> int:

@@ -1409,6 +1409,7 @@ int gpolylla_result_info(gp_result *x, gp_result_info *info) {
     info->nterminal = (int64_t)k.npoly - k.nmiddle;
     info->nties = k.nties;
     info->nflipped = x->nflipped;
+    info->loops_only = 0;
     return GP_OK;
 }
 
@@ -1419,6 +1420,7 @@ int gpolylla_result_copy(gp_result *x, int32_t *next, int32_t *prev, int32_t *se
     if (st != GP_OK) return st;
     if (x->host) {
         const size_t nh = (size_t)info.nh;
+        if ((next || prev) && info.loops_only) return GP_EINVAL;
         if (next && nh) std::memcpy(next, x->next_o, 4 * nh);
         if (prev && nh) std::memcpy(prev, x->prev_o, 4 * nh);
         if (seeds && info.npoly) std::memcpy(seeds, x->seeds, 4 * (size_t)info.npoly);

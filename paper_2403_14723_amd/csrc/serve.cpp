@@ -218,7 +218,9 @@ void start_copies(gp_server *s, Lane &L) {
         gp_result_info &info = L.infos[i];
         int rc = gpolylla_result_info(L.dev[i], &info);
         if (rc == GP_OK) {
-            const size_t words = 2 * (size_t)info.nh + (size_t)info.npoly + (size_t)info.npoly + 1 + (size_t)info.nloop_he;
+            info.loops_only = s->opts.loops_only ? 1 : 0;
+            const size_t links = info.loops_only ? 0 : 2 * (size_t)info.nh;
+            const size_t words = links + (size_t)info.npoly + (size_t)info.npoly + 1 + (size_t)info.nloop_he;
             L.blocks[i] = s->pinned->take(4 * words, &L.block_bytes[i]);
             if (!L.blocks[i]) rc = GP_ENOMEM;
         }
@@ -226,7 +228,9 @@ void start_copies(gp_server *s, Lane &L) {
             gp_result_dev dv{};
             gpolylla_result_device(L.dev[i], &dv);
             int32_t *b = static_cast<int32_t *>(L.blocks[i]);
-            const size_t nh = (size_t)info.nh, P = (size_t)info.npoly, F = (size_t)info.nloop_he;
+            // block: [next | prev] seeds loop_off loop_he
+            const size_t nh = info.loops_only ? 0 : (size_t)info.nh, P = (size_t)info.npoly,
+                         F = (size_t)info.nloop_he;
             hipError_t e = hipSuccess;
             if (nh) e = hipMemcpyAsync(b, dv.next, 4 * nh, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess && nh) e = hipMemcpyAsync(b + nh, dv.prev, 4 * nh, hipMemcpyDeviceToHost, st);
@@ -268,9 +272,9 @@ void finish(gp_server *s, Lane &L) {
         x->nv = (int32_t)info.nv;
         x->nflipped = info.nflipped;
         int32_t *b = static_cast<int32_t *>(L.blocks[i]);
-        const size_t nh = (size_t)info.nh, P = (size_t)info.npoly;
-        x->next_o = b;
-        x->prev_o = b + nh;
+        const size_t nh = info.loops_only ? 0 : (size_t)info.nh, P = (size_t)info.npoly;
+        x->next_o = info.loops_only ? nullptr : b;
+        x->prev_o = info.loops_only ? nullptr : b + nh;
         x->seeds = b + 2 * nh;
         x->loop_off = b + 2 * nh + P;
         x->loop_he = b + 2 * nh + 2 * P + 1;
@@ -359,6 +363,7 @@ int gpolylla_serve_start(gp_ctx *ctx, const gp_serve_opts *opts, gp_server **out
         if (opts->max_batch > 0) o.max_batch = opts->max_batch;
         if (opts->max_queue > 0) o.max_queue = opts->max_queue;
         if (opts->n_lanes > 0) o.n_lanes = opts->n_lanes;
+        o.loops_only = opts->loops_only ? 1 : 0;
     }
     if (o.n_lanes > 8) return GP_EINVAL;
     gp_server *s = new (std::nothrow) gp_server();

@@ -214,3 +214,28 @@ def test_latency_runs_from_the_arrival(ctx):
             assert np.array_equal(g[k], getattr(o, k)), k
         st = srv.stats()
         assert st["completed"] == 1 and st["p50_ms"] >= 50.0
+
+
+def test_loops_only_results(ctx):
+    """A loops-only server hands out the oracle's seeds and loops (Section 6.7:
+    a polygon is its seed and the loop from it) and refuses a copy of
+    next'/prev'; a mix of sizes across lanes keeps every block apart."""
+    reqs = _requests()
+    with gp.Server(ctx, pool_bytes=2 << 30, max_batch=4, n_lanes=2, loops_only=True) as srv:
+        say("[gpu] serve: loops-only results")
+        tickets = [srv.submit(m.xy, m.tri) for m in reqs]
+        got = []
+        for t in tickets:
+            r = srv.wait(t, 60000)
+            info = r.info()
+            assert info["loops_only"] == 1
+            nxt = np.empty(max(info["nh"], 1), np.int32)
+            rc = gp._load().gpolylla_result_copy(r.handle, nxt.ctypes.data, None, None, None, None)
+            assert rc == gp.GP_EINVAL
+            got.append(r.copy())
+            r.free()
+    for m, g in zip(reqs, got):
+        assert "next" not in g and "prev" not in g
+        o = oracle.polylla(m.xy, m.tri)
+        for k in ("seeds", "loop_off", "loop_he"):
+            assert np.array_equal(g[k], getattr(o, k)), (m.name, k)
