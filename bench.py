@@ -47,16 +47,19 @@ def kernel_bytes(name, nt, nv, npoly, nloop):
     48T + 8V + 8P + 4Fh + 4 that it reads or writes; label bytes and other
     intermediate state are not counted).  The shares add up to the whole
     path's bytes.  The list-driven kernels (k_repair, k_fixup, k_walk,
-    k_emit) and the tile scan move only intermediate state: no share."""
+    k_emit) and the tile scan move only intermediate state: no share.
+    k_small, the one-workgroup form for small meshes, moves all of it."""
     return {
         "k_label": 12 * nt + 8 * nv,             # org, xy in
         "k_relink": 36 * nt,                     # twin in; next', prev' out
         "k_compact": 8 * npoly + 4 * nloop + 4,  # seeds, loop_off, loop_he out
+        "k_small": algorithmic_bytes(nt, nv, npoly, nloop),
     }.get(name)
 
 
 KERNEL_BYTES_FORMULA = {"k_label": "12T + 8V (org, xy in)", "k_relink": "36T (twin in; next', prev' out)",
-                        "k_compact": "8P + 4Fh + 4 (seeds, loop_off, loop_he out)"}
+                        "k_compact": "8P + 4Fh + 4 (seeds, loop_off, loop_he out)",
+                        "k_small": "48T + 8V + 8P + 4Fh + 4 (the whole path)"}
 
 
 def profile_record(workload):

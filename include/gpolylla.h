@@ -71,7 +71,9 @@ extern "C" {
 #define GP_GRAPH 0x4u         /* mesh: replay a captured hipGraph of the kernel chain; the
                                  graph is captured on the first call for a batch shape (the
                                  list of triangle counts) and reused while the shape repeats
-                                 (up to 4 shapes per context; ignored when profiling) */
+                                 (up to 4 shapes per context; ignored when profiling, and
+                                 for a single mesh small enough to run as one workgroup,
+                                 which is one kernel launch either way) */
 #define GP_OUT_LOOPS 0x10u    /* mesh: also produce seeds / loop_off / loop_he (default on) */
 #define GP_OUT_NO_LOOPS 0x20u /* mesh: only next/prev and the counts */
 
@@ -126,6 +128,13 @@ void gpolylla_ctx_kernel_reset(gp_ctx *ctx);
  *                                        (1, 2, 4 or 8)
  *   persist=BxN                          the list-driven kernels: B threads
  *                                        per block, N blocks (1..65536)
+ *   small=N                              batches whose meshes all have at
+ *                                        most N triangles (0..4096; default
+ *                                        4096) run as one workgroup per mesh
+ *                                        with the whole pipeline in LDS, one
+ *                                        launch, where the device's LDS per
+ *                                        workgroup holds such a mesh (33
+ *                                        bytes per triangle); 0: never
  * Tiles larger than a kernel's LDS staging allows (label 4096, relink 1024,
  * compact 2048 triangles) are reduced by halving I.  Results never depend on
  * the shapes.  Applies to runs started after the call; runs already queued

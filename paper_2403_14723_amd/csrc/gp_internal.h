@@ -94,12 +94,24 @@ constexpr int kStripePad = 32;   // counters 128 bytes apart: one cache line eac
 
 // ---- launch plumbing (host side, defined in mesh_kernels.hip) ------------
 
+// k_small: a mesh of at most kSmallMaxTri triangles can run as one workgroup
+// of kSmallBlock threads with every intermediate array in LDS
+constexpr int kSmallMaxTri = 4096;
+constexpr int kSmallBlock = 1024;
+// LDS of k_small for a mesh of nt triangles: per triangle four slots (one
+// unused) of two 16-bit arrays and a 32-bit one, and a label byte
+__host__ __device__ inline size_t small_a16_bytes(int nt) { return (8 * (size_t)nt + 15) / 16 * 16; }
+__host__ __device__ inline size_t small_lab_bytes(int nt) { return ((size_t)nt + 15) / 16 * 16; }
+inline size_t small_lds_bytes(int nt) { return 4 * small_a16_bytes(nt) + small_lab_bytes(nt); }
+
 struct LaunchCfg {
     int block_label = 128, items_label = 4;
     int block_relink = 256, items_relink = 2;     // k_relink (tile <= 1024 triangles)
     int block_compact = 128, items_compact = 4;   // tile <= 2048 triangles (LDS 19 B each)
     int persistent_blocks = 2048;
     int block_persistent = 256;
+    int small_max = kSmallMaxTri;   // k_small for batches whose meshes all have at most this many triangles
+    int lds_max = 0;                // dynamic LDS bytes k_small may use on the device
 };
 
 struct RunBuffers {
@@ -126,6 +138,8 @@ struct RunBuffers {
     int32_t *wbuf;           // striped: walked loops (rotation index, then half-edges)
     int32_t *wbuf_counts;    // kStripes counters, kStripePad ints apart
     int32_t wbuf_cap;        // ints per stripe
+    int32_t max_nt;          // the largest mesh of the batch
+    bool chain_only;         // run the tiled chain even where k_small could
 };
 
 // k_walk records each chain's half-edges in LDS, up to this many; longer
@@ -144,7 +158,7 @@ inline size_t compact_lds_bytes(int tile) {
     return sizeof(int) * ((size_t)compact_he_cap(tile) + 2 * (size_t)tile);
 }
 
-enum KernelId { K_LABEL = 0, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_COUNT };
+enum KernelId { K_LABEL = 0, K_RELINK, K_REPAIR, K_FIXUP, K_WALK, K_TSCAN, K_COMPACT, K_EMIT, K_SMALL, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 
 // Per-kernel hooks so the runtime can bracket launches with events.
@@ -152,6 +166,17 @@ typedef void (*launch_hook)(void *user, int kernel_id, int after);
 
 hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s,
                            launch_hook hook, void *user);
+// Whether meshes of at most max_nt triangles fit k_small, and whether a run
+// of rb goes through it (one launch) instead of the chain.
+bool small_fits(const LaunchCfg &cfg, int max_nt);
+bool runs_small(const LaunchCfg &cfg, const RunBuffers &rb);
+// One small mesh on its own: its descriptor as a kernel argument (d.ctr may
+// be null) and its counts written to coherent host memory.
+hipError_t launch_small_one(const MeshDesc &d, MeshCounters *host, hipStream_t s);
+// Lets k_small use the current device's LDS per workgroup (lds_block bytes,
+// less its own static LDS); returns the dynamic LDS bytes it may then ask for
+// (0: none).  Once per device, before its first launch.
+int prepare_small(int lds_block);
 
 // Copies `bytes` (a multiple of 4) with a kernel on stream s; either side may
 // be coherent pinned host memory.

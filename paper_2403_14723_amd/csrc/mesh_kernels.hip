@@ -40,7 +40,7 @@
 namespace gp {
 
 const char *const kKernelNames[K_COUNT] = {"k_label",     "k_relink",  "k_repair", "k_fixup",
-                                           "k_walk", "k_tile_scan", "k_compact", "k_emit"};
+                                           "k_walk", "k_tile_scan", "k_compact", "k_emit", "k_small"};
 
 constexpr uint32_t kSeedBit = 1u << 5;
 
@@ -1620,6 +1620,468 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
 }
 
 // ---------------------------------------------------------------------------
+// k_small: the whole chain for one small mesh in one workgroup
+//
+// Below a few thousand triangles the chain's time is its eight launches and
+// the memory round trips that open each of them, not its bytes.  A mesh of at
+// most kSmallMaxTri triangles keeps every intermediate array in LDS, and one
+// workgroup runs the steps with block barriers between them:
+//   1. longest edge of every triangle (Section 6.1, Algorithm 8);
+//   2. frontier half-edges (Section 6.2, Algorithm 9);
+//   3. next' of every frontier half-edge by turning clockwise around its
+//      target (Section 6.5, Algorithm 12).  The same turns find the barrier
+//      tips (Section 6.4, Algorithm 11): a turn from next(h) that comes all
+//      the way round to twin(h) met no other frontier edge, so the target of
+//      h is a tip whose degree is the turn's length; its middle edge lies
+//      half the degree further round from twin(h).  The turns around both
+//      ends of every middle edge are then taken again with the repaired
+//      frontier;
+//   4. prev' as the inverse of next';
+//   5. every half-edge's loop minimum and its distance to it along next', by
+//      pointer doubling (Section 6.6, Algorithm 14): after a round with
+//      window w, a half-edge holds the minimum of the w half-edges from it on
+//      and how far ahead that minimum first occurs; a round that lowers no
+//      minimum has reached each loop's minimum everywhere (the windows that
+//      start w apart cover a loop and all hold the same minimum);
+//   6. seeds, loop offsets and loops in half-edge order from a block scan
+//      over the loop minima (Section 6.7).
+// In LDS a half-edge 3t + i is slot 4t + i, so next and the triangle of a
+// slot are bit operations (the order of slots is the order of half-edges),
+// and a slot's 16-bit entry holds its twin's slot with both frontier bits.
+// Each thread owns a few triangles and half-edges, and the turns of its
+// items step together so that their LDS reads overlap.  The outputs equal
+// the tiled chain's element by element.  One workgroup per mesh: a batch
+// whose meshes are all small is one launch.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kSlotNone = 0x3fff;   // no twin (4t + 3 is never a half-edge's slot)
+constexpr uint32_t kSlotF1 = 1u << 14;   // frontier (label phase)
+constexpr uint32_t kSlotF2 = 1u << 15;   // frontier after the repair
+constexpr uint32_t kNone16 = 0xffff;     // no minimum (not on a loop)
+
+__device__ __forceinline__ int slot_next(int q) { return (q & 3) == 2 ? q - 2 : q + 1; }
+__device__ __forceinline__ int slot_prev(int q) { return (q & 3) == 0 ? q + 2 : q - 1; }
+__device__ __forceinline__ int slot_he(int q) { return 3 * (q >> 2) + (q & 3); }
+
+// IT: half-edges per thread (3, 6 or 12; meshes of up to IT * kSmallBlock / 3
+// triangles), IT / 3 triangles per thread
+// The counts of a run go to the mesh's device counters and, for a run
+// launched on its own, straight to the caller's coherent host copy.
+__device__ __forceinline__ void small_counts(const MeshDesc &d, MeshCounters *host, const MeshCounters &c) {
+    if (d.ctr) *d.ctr = c;
+    if (host) *host = c;
+}
+
+template <int IT>
+__device__ __forceinline__ void small_body(const MeshDesc &d, MeshCounters *host) {
+    constexpr int TI = IT / 3;
+    extern __shared__ int4 lds_raw[];
+    __shared__ int s_scan[72];
+    __shared__ int s_cnt[4];   // tied maxima, tips, new middle edges, frontier half-edges
+    const int nt = d.nt, nh = 3 * nt, tid = threadIdx.x;
+    if (nt <= 0 || nt > TI * kSmallBlock) {   // (uniform) an empty mesh; larger ones are never launched here
+        if (tid == 0) {
+            MeshCounters c{};
+            c.err = nt != 0 ? kErrCorrupt : 0;
+            small_counts(d, host, c);
+            if (nt == 0) d.loop_off[0] = 0;
+        }
+        return;
+    }
+    if (tid < 4) s_cnt[tid] = 0;
+    char *base = reinterpret_cast<char *>(lds_raw);
+    const size_t a16 = small_a16_bytes(nt);
+    uint16_t *s_e = reinterpret_cast<uint16_t *>(base);             // twin slot | frontier bits
+    uint16_t *s_p = s_e;                                             // then doubling pointer, loop offset
+    uint16_t *s_nx = reinterpret_cast<uint16_t *>(base + a16);      // next', then loop length at minima
+    uint32_t *s_mk = reinterpret_cast<uint32_t *>(base + 2 * a16);  // minimum | distance to it << 16
+    uint8_t *s_lab = reinterpret_cast<uint8_t *>(base + 4 * a16);   // local index of the longest edge
+    int bad = 0;
+
+    // 1. longest edges; edge i of t runs from corner i to corner i + 1, and a
+    //    tie at the maximum goes to the lower edge id min(h, twin h).  All the
+    //    corner and twin loads first, then the coordinates.
+    {
+        const gcv2i xy = (gcv2i)(d.xy);
+        const TwinView twin = twin_view(d);
+        int v[TI][3], g[TI][3];
+#pragma unroll
+        for (int j = 0; j < TI; j++) {
+            const int t = tid + j * kSmallBlock, tt = t < nt ? t : 0;
+            if (!d.org8) {
+                const gcint org = (gcint)(d.org);
+#pragma unroll
+                for (int i = 0; i < 3; i++) v[j][i] = org[3 * tt + i];
+            } else {
+                const v2i r = ((GLOBAL const v2i *)d.org8)[tt];
+                const int d1 = (int)(int16_t)(r.y & 0xffff), d2 = r.y >> 16;
+                v[j][0] = r.x;
+                v[j][1] = d1 != kEsc16 ? r.x + d1 : esc_lookup(d.esc, d.esc_mask, ~(3 * tt + 1));
+                v[j][2] = d2 != kEsc16 ? r.x + d2 : esc_lookup(d.esc, d.esc_mask, ~(3 * tt + 2));
+            }
+#pragma unroll
+            for (int i = 0; i < 3; i++) g[j][i] = twin[3 * tt + i];
+        }
+        int2 p[TI][3];
+#pragma unroll
+        for (int j = 0; j < TI; j++) {
+            const bool in = tid + j * kSmallBlock < nt;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const bool ok = v[j][i] >= 0 && v[j][i] < d.nv;
+                bad |= in && !ok;
+                const v2i q = xy[ok ? v[j][i] : 0];
+                p[j][i] = make_int2(q.x, q.y);
+            }
+        }
+        int ties = 0;
+#pragma unroll
+        for (int j = 0; j < TI; j++) {
+            const int t = tid + j * kSmallBlock;
+            if (t >= nt) continue;
+            const long long l[3] = {sq_len(p[j][0], p[j][1]), sq_len(p[j][1], p[j][2]), sq_len(p[j][2], p[j][0])};
+            int best = 0;
+            long long bl = l[0];
+            int bid = (g[j][0] >= 0 && g[j][0] < 3 * t) ? g[j][0] : 3 * t;
+#pragma unroll
+            for (int i = 1; i < 3; i++) {
+                const int h = 3 * t + i, id = (g[j][i] >= 0 && g[j][i] < h) ? g[j][i] : h;
+                if (l[i] > bl || (l[i] == bl && id < bid)) {
+                    best = i;
+                    bl = l[i];
+                    bid = id;
+                }
+            }
+            ties += (l[0] == bl) + (l[1] == bl) + (l[2] == bl) > 1;
+            s_lab[t] = (uint8_t)best;
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const int gi = g[j][i];
+                const bool ok = gi >= 0 && gi < nh;
+                bad |= gi >= nh || gi < -1;
+                s_e[4 * t + i] = (uint16_t)(ok ? 4 * tri_of(gi) + (gi - 3 * tri_of(gi)) : kSlotNone);
+            }
+        }
+        if (ties) atomicAdd(&s_cnt[0], ties);
+    }
+    __syncthreads();
+
+    // the half-edges this thread owns: h = tid + j * kSmallBlock, slot q[j]
+    int q[IT];
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        const int h = tid + j * kSmallBlock;
+        q[j] = h < nh ? 4 * tri_of(h) + (h - 3 * tri_of(h)) : -1;
+    }
+
+    // 2. frontier half-edges: on the boundary, or the longest edge of neither
+    //    triangle (both bits; the repair adds to the second)
+    uint32_t front = 0;   // bit j: q[j] is a frontier half-edge (label phase, then repaired)
+    {
+        uint32_t e[IT];
+#pragma unroll
+        for (int j = 0; j < IT; j++) e[j] = q[j] >= 0 ? s_e[q[j]] : kSlotNone;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (q[j] < 0) continue;
+            const int g = (int)(e[j] & kSlotNone);
+            const bool lh = s_lab[q[j] >> 2] == (q[j] & 3);
+            const bool lg = g != (int)kSlotNone && s_lab[g >> 2] == (g & 3);
+            const bool f = g == (int)kSlotNone || (!lh && !lg);
+            if (f) {
+                s_e[q[j]] = (uint16_t)(e[j] | kSlotF1 | kSlotF2);
+                front |= 1u << j;
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. turns: next'(h) = the first frontier slot clockwise around the target
+    //    of h from next(h); a turn that ends at twin(h) found a tip
+    int nx[IT], deg[IT];
+    uint32_t tip = 0;
+    {
+        uint32_t act = front;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            nx[j] = (front >> j) & 1u ? slot_next(q[j]) : 0;
+            deg[j] = 1;
+        }
+        for (int it = 0; act && it <= 4 * nt; it++) {
+            uint32_t e[IT];
+#pragma unroll
+            for (int j = 0; j < IT; j++) e[j] = ((act >> j) & 1u) ? s_e[nx[j]] : kSlotF1;
+#pragma unroll
+            for (int j = 0; j < IT; j++) {
+                if (!((act >> j) & 1u)) continue;
+                if (e[j] & kSlotF1) {
+                    act &= ~(1u << j);
+                } else if ((e[j] & kSlotNone) == kSlotNone) {   // a non-frontier edge on the boundary: not a valid mesh
+                    act &= ~(1u << j);
+                    bad = 1;
+                } else {
+                    nx[j] = slot_next((int)(e[j] & kSlotNone));
+                    deg[j]++;
+                }
+            }
+        }
+        bad |= act != 0;
+        int tips = 0, fresh = 0;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (!((front >> j) & 1u)) continue;
+            s_nx[q[j]] = (uint16_t)nx[j];
+            const int tw = (int)(s_e[q[j]] & kSlotNone);
+            if (tw == (int)kSlotNone || nx[j] != tw) continue;
+            // a tip: its frontier half-edge is tw; the middle edge deg / 2
+            // clockwise steps further
+            int m = tw;
+            for (int k = 0; k < deg[j] / 2; k++) m = slot_next((int)(s_e[m] & kSlotNone));
+            const int mt = (int)(s_e[m] & kSlotNone);
+            if (mt == (int)kSlotNone) {
+                bad = 1;
+                continue;
+            }
+            tip |= 1u << j;
+            deg[j] = m;   // from here on: the tip's middle slot
+            const int lo = min(m, mt), hi = max(m, mt);
+            uint32_t *w32 = reinterpret_cast<uint32_t *>(s_e);
+            const uint32_t blo = kSlotF2 << (16 * (lo & 1));
+            const uint32_t old = atomicOr(&w32[lo >> 1], blo);
+            atomicOr(&w32[hi >> 1], kSlotF2 << (16 * (hi & 1)));
+            tips++;
+            fresh += !(old & blo);   // the edge's first tip counts it
+        }
+        if (tips) {
+            atomicAdd(&s_cnt[1], tips);
+            atomicAdd(&s_cnt[2], fresh);
+        }
+    }
+    __syncthreads();
+
+    // 3b. the turns around both ends of every middle edge again, over the
+    //     repaired frontier: every slot entering such a vertex.  (Two tips may
+    //     share a vertex; they write the same values.)
+    if (s_cnt[1] > 0) {   // (uniform)
+        auto turn2 = [&](int c) {
+            for (int k = 0; k <= 4 * nt; k++) {
+                const uint32_t e = s_e[c];
+                if (e & kSlotF2) return c;
+                if ((e & kSlotNone) == kSlotNone) return -1;
+                c = slot_next((int)(e & kSlotNone));
+            }
+            return -1;
+        };
+        auto fix_vertex = [&](int o0) {   // o0 leaves the vertex
+            bool open = false;
+            int o = o0;
+            for (int k = 0; k <= 4 * nt; k++) {   // clockwise
+                const int pin = slot_prev(o);
+                if (s_e[pin] & kSlotF2) {
+                    const int c = turn2(slot_next(pin));
+                    bad |= c < 0;
+                    s_nx[pin] = (uint16_t)(c < 0 ? 0 : c);
+                }
+                const int g = (int)(s_e[o] & kSlotNone);
+                if (g == (int)kSlotNone) {
+                    open = true;
+                    break;
+                }
+                o = slot_next(g);
+                if (o == o0) break;
+            }
+            if (!open) return;
+            o = o0;
+            for (int k = 0; k <= 4 * nt; k++) {   // counter-clockwise, to the other boundary edge
+                const int g = (int)(s_e[slot_prev(o)] & kSlotNone);
+                if (g == (int)kSlotNone) break;
+                o = g;
+                const int pin = slot_prev(o);
+                if (s_e[pin] & kSlotF2) {
+                    const int c = turn2(slot_next(pin));
+                    bad |= c < 0;
+                    s_nx[pin] = (uint16_t)(c < 0 ? 0 : c);
+                }
+            }
+        };
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (!((tip >> j) & 1u)) continue;
+            const int m = deg[j], mt = (int)(s_e[m] & kSlotNone);
+            fix_vertex(m);    // m leaves the tip
+            fix_vertex(mt);   // mt leaves the middle edge's other end
+        }
+        __syncthreads();
+    }
+
+    // 4. next' and prev' out (prev' is next' inverted); the doubling's first
+    //    window: m = min(q, n1), distance 1 when n1 is the smaller, p =
+    //    next'(n1).  A thread keeps its own items' values in registers.
+    int m[IT], k[IT], p[IT];
+    {
+        const gint nxo = (gint)d.next_o, pvo = (gint)d.prev_o;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (q[j] < 0) continue;
+            if (s_e[q[j]] & kSlotF2) front |= 1u << j;   // the repair's middle edges
+        }
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const int h = tid + j * kSmallBlock;
+            m[j] = kNone16;
+            k[j] = 0;
+            p[j] = q[j] >= 0 ? q[j] : 0;
+            if (q[j] < 0) continue;
+            if ((front >> j) & 1u) {
+                const int n1 = s_nx[q[j]], hn = slot_he(n1);
+                nxo[h] = hn;
+                pvo[hn] = h;
+                m[j] = min(q[j], n1);
+                k[j] = n1 < q[j] ? 1 : 0;
+                p[j] = s_nx[n1];
+            } else {
+                nxo[h] = -1;
+                pvo[h] = -1;
+            }
+        }
+    }
+    if (__syncthreads_or(bad)) {   // (uniform) no loop structure to follow; every read of s_e is done
+        if (tid == 0) {
+            MeshCounters c{};
+            c.err = kErrCorrupt;
+            small_counts(d, host, c);
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        if (q[j] < 0) continue;
+        s_mk[q[j]] = (uint32_t)m[j] | ((uint32_t)k[j] << 16);
+        s_p[q[j]] = (uint16_t)p[j];
+    }
+    __syncthreads();
+
+    // 5. doubling: each round reads its operands before any thread writes
+    bool done = false;
+    for (int round = 0, w = 2; round < 16 && !done; round++, w *= 2) {
+        uint32_t mkq[IT];
+        int pq[IT];
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            mkq[j] = s_mk[p[j]];
+            pq[j] = s_p[p[j]];
+        }
+        __syncthreads();
+        int lowered = 0;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (!((front >> j) & 1u)) continue;
+            const int mq = (int)(mkq[j] & 0xffffu);
+            if (mq < m[j]) {   // the minimum lies beyond this window: w + its distance from p
+                m[j] = mq;
+                k[j] = w + (int)(mkq[j] >> 16);
+                s_mk[q[j]] = (uint32_t)m[j] | ((uint32_t)k[j] << 16);
+                lowered = 1;
+            }
+            p[j] = pq[j];
+            s_p[q[j]] = (uint16_t)pq[j];
+        }
+        done = !__syncthreads_or(lowered);
+    }
+    bad |= !done;
+
+    // 6. loops in the order of their minima: each thread scans a contiguous
+    //    run of slots; a minimum's loop is one longer than the distance from
+    //    its successor back to it
+    constexpr int QT = 4 * TI;   // slots per thread
+    const int q0 = tid * QT;
+    int len[QT];
+    int cnt = 0, sum = 0;
+#pragma unroll
+    for (int r = 0; r < QT; r++) {
+        const int s = q0 + r;
+        len[r] = 0;
+        if ((r & 3) != 3 && (s >> 2) < nt && (int)(s_mk[s] & 0xffffu) == s) {
+            len[r] = (int)(s_mk[s_nx[s]] >> 16) + 1;
+            cnt++;
+            sum += len[r];
+        }
+    }
+    int ec, es, tc, ts;
+    block_excl_scan2(cnt, sum, ec, es, tc, ts, s_scan);
+    // a loop has at least three half-edges, and each half-edge one loop
+    const bool fits = tc <= nt && ts <= nh;
+    bad |= !fits;
+    if (fits) {
+        const gint seeds = (gint)d.seeds, loff = (gint)d.loop_off;
+#pragma unroll
+        for (int r = 0; r < QT; r++) {
+            if (!len[r]) continue;
+            const int s = q0 + r;
+            seeds[ec] = slot_he(s);
+            loff[ec] = es;
+            s_p[s] = (uint16_t)es;       // the loop's first slot
+            s_nx[s] = (uint16_t)len[r];  // and its length, for step 7
+            ec++;
+            es += len[r];
+        }
+        if (tid == 0) loff[tc] = ts;
+    }
+    __syncthreads();
+
+    // 7. every frontier half-edge into its loop's slot: the minimum first,
+    //    then the others in next' order
+    if (fits) {
+        const gint lhe = (gint)d.loop_he;
+        int off[IT], ln[IT];
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const int mc = ((front >> j) & 1u) ? m[j] : 0;
+            off[j] = s_p[mc];
+            ln[j] = s_nx[mc];
+        }
+        int nfront = 0;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (!((front >> j) & 1u)) continue;
+            nfront++;
+            const int pos = k[j] == 0 ? 0 : ln[j] - k[j];
+            if (pos < 0 || pos >= ln[j] || off[j] + pos >= ts) {
+                bad = 1;
+                continue;
+            }
+            lhe[off[j] + pos] = tid + j * kSmallBlock;
+        }
+        if (nfront) atomicAdd(&s_cnt[3], nfront);
+    }
+    const int anybad = __syncthreads_or(bad);
+    if (tid == 0) {
+        MeshCounters c{};
+        // every frontier half-edge lies on exactly one loop
+        c.err = (anybad || s_cnt[3] != ts) ? kErrCorrupt : 0;
+        c.nties = s_cnt[0];
+        c.ntips = s_cnt[1];
+        c.nmiddle = s_cnt[2];
+        c.npoly = tc;
+        c.nloop = ts;
+        small_counts(d, host, c);
+    }
+}
+
+// a batch of small meshes: one workgroup per descriptor
+template <int IT>
+__global__ void __launch_bounds__(kSmallBlock) k_small(const MeshDesc *__restrict__ descs) {
+    small_body<IT>(descs[blockIdx.x], nullptr);
+}
+
+// one small mesh, its descriptor passed by value and its counts written to
+// host memory: a call that needs nothing staged before it or copied after it
+template <int IT>
+__global__ void __launch_bounds__(kSmallBlock) k_small_one(const MeshDesc d, MeshCounters *host) {
+    small_body<IT>(d, host);
+}
+
+// ---------------------------------------------------------------------------
 // small copies between device memory and coherent pinned host memory (the
 // descriptor table before a run, the per-mesh counters after it): a kernel
 // in stream order instead of the runtime's copy path
@@ -1698,12 +2160,71 @@ hipError_t launch_relink(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t
     return hipGetLastError();
 }
 
+bool small_fits(const LaunchCfg &cfg, int max_nt) {
+    return max_nt >= 0 && max_nt <= cfg.small_max && max_nt <= kSmallMaxTri &&
+           small_lds_bytes(max_nt) <= (size_t)cfg.lds_max;
+}
+
+bool runs_small(const LaunchCfg &cfg, const RunBuffers &rb) { return !rb.chain_only && small_fits(cfg, rb.max_nt); }
+
+hipError_t launch_small_one(const MeshDesc &d, MeshCounters *host, hipStream_t s) {
+    const dim3 grid(1), block(kSmallBlock);
+    const size_t lds = small_lds_bytes(d.nt);
+    if (d.nt <= kSmallBlock)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_one<3>), grid, block, lds, s, d, host);
+    else if (d.nt <= 2 * kSmallBlock)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_one<6>), grid, block, lds, s, d, host);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_one<12>), grid, block, lds, s, d, host);
+    return hipGetLastError();
+}
+
+int prepare_small(int lds_block) {
+    const void *const fns[6] = {reinterpret_cast<const void *>(&k_small<3>),
+                                reinterpret_cast<const void *>(&k_small<6>),
+                                reinterpret_cast<const void *>(&k_small<12>),
+                                reinterpret_cast<const void *>(&k_small_one<3>),
+                                reinterpret_cast<const void *>(&k_small_one<6>),
+                                reinterpret_cast<const void *>(&k_small_one<12>)};
+    int fixed = 0;
+    for (const void *f : fns) {
+        hipFuncAttributes a{};
+        if (hipFuncGetAttributes(&a, f) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        fixed = (int)a.sharedSizeBytes > fixed ? (int)a.sharedSizeBytes : fixed;
+    }
+    const int dyn = lds_block - fixed;
+    if (dyn <= 0) return 0;
+    if (dyn > 65536 - fixed)
+        for (const void *f : fns)
+            if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+                (void)hipGetLastError();
+                return 65536 - fixed;
+            }
+    return dyn;
+}
+
 hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, launch_hook hook,
                            void *user) {
     auto H = [&](int k, int after) {
         if (hook) hook(user, k, after);
     };
     if (rb.nmesh <= 0) return hipSuccess;
+    if (runs_small(cfg, rb)) {   // every mesh fits one workgroup: one launch
+        const dim3 grid(rb.nmesh), block(kSmallBlock);
+        const size_t lds = small_lds_bytes(rb.max_nt);
+        H(K_SMALL, 0);
+        if (rb.max_nt <= kSmallBlock)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small<3>), grid, block, lds, s, rb.descs);
+        else if (rb.max_nt <= 2 * kSmallBlock)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small<6>), grid, block, lds, s, rb.descs);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small<12>), grid, block, lds, s, rb.descs);
+        H(K_SMALL, 1);
+        return hipGetLastError();
+    }
     const int pb = cfg.persistent_blocks, pt = cfg.block_persistent;
     const int cmp_tb = cfg.block_compact * cfg.items_compact;   // triangles per compaction tile
 

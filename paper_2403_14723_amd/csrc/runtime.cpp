@@ -174,7 +174,7 @@ hipError_t stage_to_device(gp_ctx *c, void *dst, const void *src, size_t n) {
 void run_destroy(RunState *r) {
     pinned_give(r->ctx, r->host_ctrs, r->host_ctrs_bytes);
     delete r->dbg;
-    if (r->done) (void)hipEventDestroy(r->done);
+    if (r->done) r->ctx->done_events.push_back(r->done);   // completed (or never recorded): reusable
     delete r;
 }
 
@@ -352,7 +352,10 @@ void layout_scratch(const PlanSizes &p, const gp::MeshDesc *descs, int n, void *
     rb->wbuf = at.take<int32_t>(p.wbuf_cap * S + 32);   // + a 16-byte-group overread at the end
     rb->wbuf_counts = at.take<int32_t>(S * gp::kStripePad);
     rb->wbuf_cap = (int32_t)p.wbuf_cap;
+    rb->max_nt = 0;
+    rb->chain_only = false;
     for (int i = 0; i < n; i++) {
+        rb->max_nt = std::max(rb->max_nt, descs[i].nt);
         tflag[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));
         pl[i] = at.take<uint8_t>(align_up(descs[i].nt + 4, 4));   // whole words: k_walk claims by OR
         lpos[i] = at.take<int32_t>(descs[i].nt + 1);
@@ -863,6 +866,16 @@ int parse_launch_spec(const char *spec, gp::LaunchCfg *cfg) {
         const std::string item = sp.substr(p0, p1 - p0);
         p0 = p1 + 1;
         const size_t eq = item.find('='), x = item.find('x', eq == std::string::npos ? 0 : eq);
+        if (eq != std::string::npos && item.compare(0, eq, "small") == 0) {
+            // small=N: meshes of at most N triangles run as one workgroup (0: never)
+            const std::string sn = item.substr(eq + 1);
+            if (sn.empty() || sn.size() > 6 || sn.find_first_not_of("0123456789") != std::string::npos)
+                return GP_EINVAL;
+            const int n = std::atoi(sn.c_str());
+            if (n > gp::kSmallMaxTri) return GP_EINVAL;
+            g.small_max = n;
+            continue;
+        }
         if (eq == std::string::npos || x == std::string::npos) return GP_EINVAL;
         const std::string k = item.substr(0, eq), sb = item.substr(eq + 1, x - eq - 1), si = item.substr(x + 1);
         if (sb.empty() || si.empty() || sb.size() > 6 || si.size() > 6 ||
@@ -900,6 +913,26 @@ int parse_launch_spec(const char *spec, gp::LaunchCfg *cfg) {
     return GP_OK;
 }
 
+// Dynamic LDS one k_small workgroup may use on a device (the current one),
+// from the device's per-workgroup limit; looked up once per device.
+int small_lds_limit(int device) {
+    static std::mutex mu;
+    static int limit[kMaxDevices];
+    static bool known[kMaxDevices];
+    std::lock_guard<std::mutex> lk(mu);
+    if (device < 0 || device >= kMaxDevices) return 0;
+    if (!known[device]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v < 0) {
+            (void)hipGetLastError();
+            v = 0;
+        }
+        limit[device] = v > 0 ? gp::prepare_small(v) : 0;
+        known[device] = true;
+    }
+    return limit[device];
+}
+
 }  // namespace
 
 int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
@@ -916,6 +949,7 @@ int gpolylla_ctx_create(int device, const gp_ctx_opts *opts, gp_ctx **out) {
     c->device = device;
     DeviceGuard g(device);
     noalloc_setup(device);
+    c->cfg.lds_max = small_lds_limit(device);
     if (opts) {
         c->pool.cap = opts->pool_bytes;
         c->profile = opts->profile != 0;
@@ -963,6 +997,7 @@ void gpolylla_ctx_destroy(gp_ctx *c) {
         c->graphs = nullptr;
     }
     for (auto e : c->spare_events) (void)hipEventDestroy(e);
+    for (auto e : c->done_events) (void)hipEventDestroy(e);
     c->pool.destroy();
     for (auto &kv : c->pinned_free) (void)hipHostFree(kv.second);
     for (auto &sl : c->ring) {
@@ -1051,10 +1086,10 @@ int gpolylla_ctx_set_launch(gp_ctx *c, const char *spec) {
 int gpolylla_ctx_get_launch(const gp_ctx *c, char *buf, int32_t cap) {
     if (!c) return GP_EINVAL;
     const gp::LaunchCfg &g = c->cfg;
-    char tmp[160];
-    const int n = std::snprintf(tmp, sizeof tmp, "label=%dx%d,relink=%dx%d,compact=%dx%d,persist=%dx%d",
+    char tmp[192];
+    const int n = std::snprintf(tmp, sizeof tmp, "label=%dx%d,relink=%dx%d,compact=%dx%d,persist=%dx%d,small=%d",
                                 g.block_label, g.items_label, g.block_relink, g.items_relink, g.block_compact,
-                                g.items_compact, g.block_persistent, g.persistent_blocks);
+                                g.items_compact, g.block_persistent, g.persistent_blocks, g.small_max);
     if (buf && cap > 0) {
         const int m = n < cap - 1 ? n : cap - 1;
         std::memcpy(buf, tmp, (size_t)m);
@@ -1173,14 +1208,18 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     if (rc != GP_OK) return rc;
     reap_retired(c, false);
 
+    // one small mesh runs as one kernel launch with its descriptor as the
+    // argument and its counts written straight to host memory: no scratch,
+    // nothing staged, no graph (there is one kernel to launch)
+    const bool small_one = n == 1 && !c->profile && !c->debug && gp::small_fits(c->cfg, meshes[0]->nt);
     // scratch: per call from the pool, or owned by a cached graph
-    const bool use_graph = (out_flags & GP_GRAPH) && !c->profile && !c->debug;
+    const bool use_graph = (out_flags & GP_GRAPH) && !c->profile && !c->debug && !small_one;
     GraphEntry *ge = nullptr;
     void *p_tmp = nullptr;
     if (use_graph) {
         rc = graph_entry(c, plan, &ge);
         if (rc != GP_OK) return rc;
-    } else {
+    } else if (!small_one) {
         rc = c->pool.alloc(plan.tmp_bytes, &p_tmp);
         if (rc != GP_OK) return rc;
     }
@@ -1197,7 +1236,10 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         r->host_ctrs = static_cast<gp::MeshCounters *>(pinned_take(c, r->host_ctrs_bytes));
         if (!r->host_ctrs) rc = GP_ENOMEM;
     }
-    if (rc == GP_OK && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
+    if (rc == GP_OK && !c->done_events.empty()) {
+        r->done = c->done_events.back();
+        c->done_events.pop_back();
+    } else if (rc == GP_OK && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         r->done = nullptr;
         rc = GP_EHIP;
@@ -1216,9 +1258,10 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         tflag = ge->tflag;
         pl = ge->pl;
         lpos = ge->lpos;
-    } else {
+    } else if (!small_one) {
         layout_scratch(plan, plan.descs.data(), n, p_tmp, &rb, tflag.data(), pl.data(), lpos.data());
         rb.compact = plan.compact;
+        rb.chain_only = c->debug;   // the snapshots are of the chain's intermediate stages
     }
     Arena ao{static_cast<char *>(r->out_block), plan.out_bytes, 0};
     std::vector<gp_result *> res(n, nullptr);
@@ -1255,7 +1298,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         d.tflag = tflag[i];
         d.pl = pl[i];
         d.lpos = lpos[i];
-        d.ctr = rb.ctrs + i;
+        d.ctr = small_one ? nullptr : rb.ctrs + i;
     }
     hipStream_t s = c->stream;
     int err = GP_OK;
@@ -1265,7 +1308,7 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
     const size_t dbytes = sizeof(gp::MeshDesc) * n;
     const bool same = ge && ge->staged.size() == descs.size() &&
                       std::memcmp(ge->staged.data(), descs.data(), dbytes) == 0;
-    if (!same) {
+    if (!same && !small_one) {
         if (stage_to_device(c, const_cast<gp::MeshDesc *>(rb.descs), descs.data(), dbytes) != hipSuccess)
             err = GP_EHIP;
         else if (ge)
@@ -1299,15 +1342,16 @@ int gpolylla_mesh_batch(gp_ctx *c, const gp_mesh *const *meshes, int32_t n, uint
         }
     }
     if (err == GP_OK) {
-        hipError_t e = ge ? hipGraphLaunch(ge->exec, s)
-                          : c->debug ? gp::launch_pipeline(c->cfg, rb, s, debug_hook, &dh)
-                                     : gp::launch_pipeline(c->cfg, rb, s, c->profile ? profile_hook : nullptr, c);
+        hipError_t e = small_one ? gp::launch_small_one(descs[0], r->host_ctrs, s)
+                       : ge      ? hipGraphLaunch(ge->exec, s)
+                       : c->debug ? gp::launch_pipeline(c->cfg, rb, s, debug_hook, &dh)
+                                  : gp::launch_pipeline(c->cfg, rb, s, c->profile ? profile_hook : nullptr, c);
         if (e != hipSuccess) err = GP_EHIP;
     }
-    if (err == GP_OK && (gp::launch_copy_words(r->host_ctrs, rb.ctrs, sizeof(gp::MeshCounters) * n, s) !=
-                             hipSuccess ||
-                         hipEventRecord(r->done, s) != hipSuccess))
+    if (err == GP_OK && !small_one &&
+        gp::launch_copy_words(r->host_ctrs, rb.ctrs, sizeof(gp::MeshCounters) * n, s) != hipSuccess)
         err = GP_EHIP;
+    if (err == GP_OK && hipEventRecord(r->done, s) != hipSuccess) err = GP_EHIP;
     // per-call temporaries go back to the pool; later users are ordered after
     // this run on the same stream
     c->pool.release(p_tmp);

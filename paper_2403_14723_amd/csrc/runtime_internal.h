@@ -179,6 +179,7 @@ struct gp_ctx {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> spare_events;
+    std::vector<hipEvent_t> done_events;   // completion events of finished runs, for reuse
     hipEvent_t open_ev[gp::K_COUNT] = {};
     double kms[gp::K_COUNT] = {};
     int64_t kcount[gp::K_COUNT] = {};

@@ -34,6 +34,8 @@ def test_kernel_shares_add_up_to_the_whole_path():
         assert b.kernel_bytes("k_relink", nt, nv, p, fh) == 36 * nt
         for k in ("k_repair", "k_fixup", "k_walk", "k_emit", "k_tile_scan"):
             assert b.kernel_bytes(k, nt, nv, p, fh) is None
+        # the one-workgroup form of small meshes moves the whole path's bytes
+        assert b.kernel_bytes("k_small", nt, nv, p, fh) == b.algorithmic_bytes(nt, nv, p, fh)
 
 
 def test_cpu_baseline_reports_its_host():

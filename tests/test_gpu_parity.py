@@ -274,11 +274,12 @@ def test_graph_replays_match_eager(ctx):
 
 def test_launch_spec_roundtrip_and_errors():
     with gp.Context(0) as c:
-        c.set_launch("label=512x2,relink=128x4,compact=256x8,persist=256x512")
-        assert c.launch() == "label=512x2,relink=128x4,compact=256x8,persist=256x512"
+        c.set_launch("label=512x2,relink=128x4,compact=256x8,persist=256x512,small=1000")
+        assert c.launch() == "label=512x2,relink=128x4,compact=256x8,persist=256x512,small=1000"
         before = c.launch()
         for bad in ("label=100x2", "relink=256x3", "nope=256x2", "label=256", "label=x2", "label=256x2,,x",
-                    "compact=2048x1", "persist=256x0", "label=256x2;relink=256x2"):
+                    "compact=2048x1", "persist=256x0", "label=256x2;relink=256x2", "small=4097", "small=",
+                    "small=-1", "small=1x2"):
             with pytest.raises(gp.GPolyllaError) as e:
                 c.set_launch(bad)
             assert e.value.code == gp.GP_EINVAL, bad
