@@ -936,24 +936,39 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
             mesh = e.mesh;
             const MeshDesc &d = descs[e.mesh];
             const TwinView twin = twin_view(d);
-            // a: the only frontier edge at the tip v = target(e.he), leaving v
+            // a: the only frontier edge at the tip v = target(e.he), leaving v.
+            // The middle edge is the outgoing half-edge floor(deg / 2)
+            // clockwise steps from a.  Turning clockwise (c) and counter-
+            // clockwise (b) from a at once, the two meet there after about
+            // deg / 2 steps: c one step short of b after k steps means deg =
+            // 2k + 1 and the middle is c; c and b equal after k + 1 steps
+            // means deg = 2k + 2 and the middle is that half-edge.
             a = twin[e.he];
             bool err = a < 0;
-            int deg = 0, r = a;
-            while (!err) {   // degree: a full clockwise turn around v
-                const int g = twin[r];
-                if (g < 0 || ++deg > kRotGuard) {
-                    err = true;
-                    break;
-                }
-                r = he_next(g);
-                if (r == a) break;
-            }
             if (!err) {
-                m = a;
-                for (int s2 = 0; s2 < deg / 2; s2++) m = he_next(twin[m]);
-                mt = twin[m];
-                err = mt < 0;
+                int c = a, b = a;
+                for (int k = 0;; k++) {
+                    const int gc = twin[c], gb = twin[he_prev(b)];   // both loads in flight
+                    if (gc < 0 || gb < 0 || k > kRotGuard) {
+                        err = true;
+                        break;
+                    }
+                    const int c1 = he_next(gc);
+                    if (c1 == b && k > 0) {   // odd degree
+                        m = c;
+                        break;
+                    }
+                    if (c1 == gb) {   // even degree
+                        m = c1;
+                        break;
+                    }
+                    c = c1;
+                    b = gb;
+                }
+                if (!err) {
+                    mt = twin[m];
+                    err = mt < 0;
+                }
             }
             if (err) {
                 atomicOr(&d.ctr->err, kErrCorrupt);
@@ -1022,21 +1037,29 @@ __device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
     return ok;
 }
 
-// Every fix-up anchor o (a half-edge leaving vertex x) gets a group of 32
-// lanes: lane j < 16 takes the outgoing half-edge j clockwise steps from o,
-// lane 16 + k the one k + 1 counter-clockwise steps away (only when the
-// clockwise turn met the boundary, i.e. x is on it), and each lane fixes
-// next'/prev' at its half-edge, so the turns around x run side by side.  The
-// last lane of each side continues past 16 steps on its own.
+// Every fix-up anchor o (a half-edge leaving vertex x) gets a group of G
+// lanes (G = 16: four anchors per wave): lane j < G/2 takes the outgoing
+// half-edge j clockwise steps from o, lane G/2 + k the one k + 1
+// counter-clockwise steps away (only when the clockwise turn met the
+// boundary, i.e. x is on it), and each lane fixes next'/prev' at its
+// half-edge, so the turns around x run side by side.  The last lane of each
+// side continues past G/2 steps on its own.
+constexpr int kFixLanes = 16;
+
+template <int G>
 __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *fixes,
                         int cap_fix) {
+    static_assert(G == 16 || G == 32, "lane groups of 16 or 32");
+    constexpr int H = G / 2;
+    constexpr unsigned long long kGroup = G == 32 ? 0xffffffffull : 0xffffull;
+    constexpr unsigned long long kCw = G == 32 ? 0x0000ffff0000ffffull : 0x00ff00ff00ff00ffull;
     const int nfix = min(rc->nfix, cap_fix);
-    const int lane = __lane_id(), gl = lane & 31;
-    const unsigned long long gmask = (lane < 32) ? 0x00000000ffffffffull : 0xffffffff00000000ull;
-    const unsigned long long cwmask = gmask & 0x0000ffff0000ffffull;   // lanes 0-15 of each group
-    const int groups = gridDim.x * (blockDim.x / 32);
-    for (int qb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 2; qb < nfix; qb += groups) {
-        const int q = qb + (lane >> 5);
+    const int lane = __lane_id(), gl = lane & (G - 1);
+    const unsigned long long gmask = kGroup << (lane & ~(G - 1));
+    const unsigned long long cwmask = gmask & kCw;   // the clockwise lanes of each group
+    const int groups = gridDim.x * (blockDim.x / G);
+    for (int qb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave / G); qb < nfix; qb += groups) {
+        const int q = qb + lane / G;
         const bool valid = q < nfix;
         const ListEntry en = valid ? fixes[q] : ListEntry{0, 0};
         const MeshDesc &d = descs[en.mesh];
@@ -1044,7 +1067,7 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
         const int o = en.he;
         bool ok = true, have = false, boundary = false;
         int e = o;
-        if (valid && gl < 16) {   // clockwise: e <- next(twin(e)), gl steps
+        if (valid && gl < H) {   // clockwise: e <- next(twin(e)), gl steps
             have = true;
             for (int s2 = 0; s2 < gl; s2++) {
                 const int g = twin[e];
@@ -1060,9 +1083,9 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
                 }
             }
         }
-        // past 16 steps clockwise: the last lane goes on alone (and finds the
+        // past H steps clockwise: the last lane goes on alone (and finds the
         // boundary if the turn reaches it there)
-        if (have && gl == 15) {
+        if (have && gl == H - 1) {
             int f = e;
             for (int steps = 0;; steps++) {
                 const int g = twin[f];
@@ -1080,9 +1103,9 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
             }
         }
         const bool open = (__ballot(boundary) & cwmask & gmask) != 0ull;
-        if (valid && gl >= 16 && open) {   // counter-clockwise: e <- twin(prev(e)), gl - 15 steps
+        if (valid && gl >= H && open) {   // counter-clockwise: e <- twin(prev(e)), gl - H + 1 steps
             have = true;
-            for (int s2 = 0; s2 <= gl - 16; s2++) {
+            for (int s2 = 0; s2 <= gl - H; s2++) {
                 const int g = twin[he_prev(e)];
                 if (g < 0) {
                     have = false;
@@ -1092,8 +1115,8 @@ __global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, con
             }
         }
         if (have) ok &= fix_around(d, e);
-        // past 16 steps counter-clockwise: the last lane goes on alone
-        if (have && gl == 31) {
+        // past H steps counter-clockwise: the last lane goes on alone
+        if (have && gl == G - 1) {
             for (int steps = 0;; steps++) {
                 const int g = twin[he_prev(e)];
                 if (g < 0) break;
@@ -1128,16 +1151,24 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
 
 // Every entry of the walk list: from the seed to a frontier half-edge of its
 // polygon (a frontier half-edge of the seed's own triangle if it has one),
-// around the loop, and the loop recorded.  Each thread keeps ITEMS loops in
-// flight and advances them in lock-step; each loop's next' array and bound
-// sit in registers.  Every chain also writes the half-edges it visits to an
-// LDS buffer, so the walker that claims a loop of at most BUF half-edges
-// copies it to the scratch pool (rotation index of the minimum, then the
-// half-edges in walk order) and k_compact places it without walking it
-// again.  Whole waves iterate together: the pool is reserved once per wave
-// and step, for every loop that closed in that step and fits the buffer,
-// while the claims are still in flight (a walker that loses the claim leaves
-// its space unused).
+// around the loop, and the loop recorded.  A loop still open after
+// kWalkBoth steps is walked from both ends from then on: forward along
+// next' and backward along prev' from the start, the two loads of a step in
+// flight together, until the ends meet, so a long loop of len half-edges
+// takes about len / 2 dependent steps (short loops, the most, read no
+// prev').  Each
+// thread keeps ITEMS loops in flight and advances them in lock-step.  Every
+// chain also writes the half-edges it visits to an LDS buffer (forward ones
+// from the front, backward ones from the back), so the walker that claims a
+// loop of at most BUF half-edges copies it to the scratch pool (rotation
+// index of the minimum, then the half-edges in loop order from the first
+// backward one) and k_compact places it without walking it again.  Whole
+// waves iterate together: the pool is reserved once per wave and step, for
+// every loop that closed in that step and fits the buffer, while the claims
+// are still in flight (a walker that loses the claim leaves its space
+// unused).
+constexpr int kWalkBoth = 8;
+
 template <int ITEMS, int BUF>
 __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs, const ListEntry *walk,
                                               const int32_t *walk_counts, int walk_cap, uint64_t *agg,
@@ -1150,20 +1181,26 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
     const int lane = __lane_id(), tid = threadIdx.x;
     const int wstripe = ((blockIdx.x * blockDim.x + tid) >> 6) % kStripes;   // this wave's pool stripe
     for (int b0 = blockIdx.x * blockDim.x; b0 < total; b0 += nthreads * ITEMS) {   // block-uniform
-        gcint nx[ITEMS];
-        int mesh[ITEMS], cur[ITEMS], start[ITEMS], mn[ITEMS], rot[ITEMS], len[ITEMS], lim[ITEMS];
+        gcint nx[ITEMS], pv[ITEMS];
+        // forward end fc (fa half-edges taken, from the start on), backward
+        // end bc (bb taken before the start; the start itself while bb == 0);
+        // the minimum so far and where: forward index, or ~backward index
+        int mesh[ITEMS], fc[ITEMS], bc[ITEMS], fa[ITEMS], bb[ITEMS], mn[ITEMS], mpos[ITEMS], lim[ITEMS];
+        bool live[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
-            start[j] = cur[j] = mn[j] = -1;
-            rot[j] = len[j] = lim[j] = 0;
+            fc[j] = bc[j] = mn[j] = -1;
+            fa[j] = bb[j] = mpos[j] = lim[j] = 0;
             mesh[j] = 0;
-            nx[j] = nullptr;
+            live[j] = false;
+            nx[j] = pv[j] = nullptr;
             const int g = b0 + tid + j * nthreads;
             if (g >= total) continue;
             const ListEntry e = walk[striped_index(s_pref, walk_cap, g)];
             const MeshDesc &d = descs[e.mesh];
             mesh[j] = e.mesh;
             nx[j] = (gcint)d.next_o;
+            pv[j] = (gcint)d.prev_o;
             lim[j] = 3 * d.nt;
             const int t = tri_of(e.he);
             const uint32_t f = ((gcu8)d.tflag)[t];
@@ -1176,37 +1213,58 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                 atomicOr(&d.ctr->err, kErrCorrupt);
                 continue;
             }
-            start[j] = cur[j] = mn[j] = st;
+            fc[j] = bc[j] = mn[j] = st;
+            fa[j] = 1;
+            live[j] = true;
+            s_buf[j * 256 + tid] = st;
         }
         while (true) {
             bool active = false;
-            int need[ITEMS];
+            int need[ITEMS], len[ITEMS], rot[ITEMS];
             bool closed[ITEMS];
             uint32_t claim[ITEMS];
 #pragma unroll
             for (int j = 0; j < ITEMS; j++) {
-                need[j] = 0;
+                need[j] = len[j] = rot[j] = 0;
                 closed[j] = false;
                 claim[j] = 0;
-                if (start[j] < 0) continue;
-                if (len[j] < BUF) s_buf[len[j] * kSlots + j * 256 + tid] = cur[j];
-                if (cur[j] < mn[j]) {
-                    mn[j] = cur[j];
-                    rot[j] = len[j];
+                if (!live[j]) continue;
+                const bool two = fa[j] >= kWalkBoth;
+                const int nf = nx[j][fc[j]], nb = two ? pv[j][bc[j]] : 0;
+                bool done = nf == bc[j];   // the forward end reached the backward one
+                if (!done && nf >= 0) {
+                    fc[j] = nf;
+                    if (fa[j] < BUF) s_buf[fa[j] * kSlots + j * 256 + tid] = nf;
+                    if (nf < mn[j]) {
+                        mn[j] = nf;
+                        mpos[j] = fa[j];
+                    }
+                    ++fa[j];
+                    done = two && nb == nf;   // the backward end reached the forward one
+                    if (two && !done && nb >= 0) {
+                        bc[j] = nb;
+                        if (bb[j] < BUF) s_buf[(BUF - 1 - bb[j]) * kSlots + j * 256 + tid] = nb;
+                        if (nb < mn[j]) {
+                            mn[j] = nb;
+                            mpos[j] = ~bb[j];
+                        }
+                        ++bb[j];
+                    }
                 }
-                ++len[j];
-                cur[j] = nx[j][cur[j]];
-                if (cur[j] < 0 || len[j] > lim[j]) {
+                len[j] = fa[j] + bb[j];
+                if (nf < 0 || nb < 0 || len[j] > lim[j]) {
                     atomicOr(&descs[mesh[j]].ctr->err, kErrCorrupt);
-                    start[j] = -1;
+                    live[j] = false;
                     continue;
                 }
-                if (cur[j] == start[j]) {
+                if (done) {
                     closed[j] = true;
+                    // position of the minimum in loop order from the first backward half-edge
+                    rot[j] = mpos[j] >= 0 ? bb[j] + mpos[j] : bb[j] - 1 - ~mpos[j];
                     claim[j] = claim_issue(descs[mesh[j]], mn[j], len[j]);
                     // whole 16-byte groups, so k_compact reads a loop with vector loads
                     need[j] = len[j] <= BUF ? (len[j] + 4) & ~3 : 0;
-                    start[j] = -1;
+                    live[j] = false;
                     continue;
                 }
                 active = true;
@@ -1230,7 +1288,11 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                 if (won && need[j] && room) {
                     const gint out = (gint)wbuf + pos;
                     out[0] = rot[j];
-                    for (int k = 0; k < len[j]; k++) out[1 + k] = s_buf[k * kSlots + j * 256 + tid];
+                    // the backward half-edges (from the back of the buffer), then the forward ones
+                    for (int k = 0; k < len[j]; k++) {
+                        const int at = k < bb[j] ? BUF - bb[j] + k : k - bb[j];
+                        out[1 + k] = s_buf[at * kSlots + j * 256 + tid];
+                    }
                     const int tm = tri_of(mn[j]);
                     ((gint)d.lpos)[tm] = pos;
                     atomicOr(reinterpret_cast<uint32_t *>(d.tflag) + (tm >> 2), kStoredBit << (8 * (tm & 3)));
@@ -2252,7 +2314,8 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_REPAIR, 1);
 
     H(K_FIXUP, 0);
-    hipLaunchKernelGGL(k_fixup, dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.fixes, rb.cap_fix);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fixup<kFixLanes>), dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.fixes,
+                       rb.cap_fix);
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
