@@ -119,32 +119,6 @@ __device__ __forceinline__ bool is_frontier(const uint8_t *__restrict__ tflag, i
     return fbit(tflag[t], h - 3 * t);
 }
 
-// Turning from candidate c (label fc of its triangle): the first frontier
-// half-edge met.  NEXT: clockwise around the target of the half-edge being
-// linked, c <- next(twin(c)); !NEXT: the mirror, c <- prev(twin(c)).  A
-// non-frontier edge is interior, so twin(c) exists.  -1 when the guard trips.
-template <bool NEXT>
-__device__ __forceinline__ int turn(const TwinView &twin, const uint8_t *__restrict__ tflag, int c, uint32_t fc) {
-    for (int k = 0; k < kRotGuard; k++) {
-        const int tc = c / 3;
-        if (fbit(fc, c - 3 * tc)) return c;
-        const int g = twin[c];
-        if (g < 0) return -1;
-        c = NEXT ? he_next(g) : he_prev(g);
-        fc = tflag[c / 3];
-    }
-    return -1;
-}
-
-__device__ __forceinline__ int turn_next(const TwinView &twin, const uint8_t *__restrict__ tflag, int h) {
-    const int c = he_next(h);
-    return turn<true>(twin, tflag, c, tflag[c / 3]);
-}
-__device__ __forceinline__ int turn_prev(const TwinView &twin, const uint8_t *__restrict__ tflag, int h) {
-    const int c = he_prev(h);
-    return turn<false>(twin, tflag, c, tflag[c / 3]);
-}
-
 // ---------------------------------------------------------------------------
 // wave / block helpers
 // ---------------------------------------------------------------------------
@@ -1018,117 +992,95 @@ __global__ void k_repair(const MeshDesc *__restrict__ descs, RunCounters *rc, co
 // k_fixup: recompute next/prev of every frontier half-edge at a vertex
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool fix_around(const MeshDesc &d, int e) {
-    // e leaves the vertex x; prev(e) enters x in the same triangle
-    const TwinView twin = twin_view(d);
-    const uint8_t *__restrict__ tflag = d.tflag;
-    const int p = he_prev(e);
-    bool ok = true;
-    if (is_frontier(tflag, p)) {
-        const int n = turn_next(twin, tflag, p);
-        ok &= n >= 0;
-        d.next_o[p] = n;
+// One lane per anchor o0 (a half-edge leaving a vertex x at either end of a
+// new frontier edge) takes next'/prev' around x again in one sweep.  Around
+// x, the outgoing half-edge o is preceded in its triangle by prev(o), which
+// enters x; next' of a frontier prev(o) is the nearest frontier outgoing
+// half-edge at o or clockwise after it, and prev' is its inverse.  So a
+// sweep counter-clockwise (o <- twin(prev(o))) from a frontier outgoing
+// half-edge, keeping the last frontier outgoing half-edge it passed, sets
+// them all with one dependent load per step.  A vertex on the boundary is
+// swept from where the clockwise search stopped to the counter-clockwise
+// end, then from the clockwise end back.  Anchors at one vertex write the
+// same values.
+__device__ __forceinline__ void sweep_step(gcu8 tfl, gint nxo, gint pvo, int o, int &cur) {
+    const int t = tri_of(o), pin = he_prev(o);
+    const uint32_t f = tfl[t];
+    if (fbit(f, o - 3 * t)) cur = o;
+    if (fbit(f, pin - 3 * t)) {
+        nxo[pin] = cur;
+        pvo[cur] = pin;
     }
-    if (is_frontier(tflag, e)) {
-        const int q = turn_prev(twin, tflag, e);
-        ok &= q >= 0;
-        d.prev_o[e] = q;
-    }
-    return ok;
 }
 
-// Every fix-up anchor o (a half-edge leaving vertex x) gets a group of G
-// lanes (G = 16: four anchors per wave): lane j < G/2 takes the outgoing
-// half-edge j clockwise steps from o, lane G/2 + k the one k + 1
-// counter-clockwise steps away (only when the clockwise turn met the
-// boundary, i.e. x is on it), and each lane fixes next'/prev' at its
-// half-edge, so the turns around x run side by side.  The last lane of each
-// side continues past G/2 steps on its own.
-constexpr int kFixLanes = 16;
-
-template <int G>
-__global__ void k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc, const ListEntry *fixes,
-                        int cap_fix) {
-    static_assert(G == 16 || G == 32, "lane groups of 16 or 32");
-    constexpr int H = G / 2;
-    constexpr unsigned long long kGroup = G == 32 ? 0xffffffffull : 0xffffull;
-    constexpr unsigned long long kCw = G == 32 ? 0x0000ffff0000ffffull : 0x00ff00ff00ff00ffull;
+__global__ void __launch_bounds__(256) k_fixup(const MeshDesc *__restrict__ descs, RunCounters *rc,
+                                               const ListEntry *fixes, int cap_fix) {
     const int nfix = min(rc->nfix, cap_fix);
-    const int lane = __lane_id(), gl = lane & (G - 1);
-    const unsigned long long gmask = kGroup << (lane & ~(G - 1));
-    const unsigned long long cwmask = gmask & kCw;   // the clockwise lanes of each group
-    const int groups = gridDim.x * (blockDim.x / G);
-    for (int qb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (kWave / G); qb < nfix; qb += groups) {
-        const int q = qb + lane / G;
-        const bool valid = q < nfix;
-        const ListEntry en = valid ? fixes[q] : ListEntry{0, 0};
+    const int stride = gridDim.x * blockDim.x;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nfix; q += stride) {
+        const ListEntry en = fixes[q];
         const MeshDesc &d = descs[en.mesh];
         const TwinView twin = twin_view(d);
-        const int o = en.he;
-        bool ok = true, have = false, boundary = false;
-        int e = o;
-        if (valid && gl < H) {   // clockwise: e <- next(twin(e)), gl steps
-            have = true;
-            for (int s2 = 0; s2 < gl; s2++) {
-                const int g = twin[e];
-                if (g < 0) {
-                    boundary = true;
-                    have = false;
-                    break;
-                }
-                e = he_next(g);
-                if (e == o) {   // around a closed fan in fewer steps: no edge of its own
-                    have = false;
-                    break;
-                }
+        const gcu8 tfl = (gcu8)d.tflag;
+        const gint nxo = (gint)d.next_o, pvo = (gint)d.prev_o;
+        bool ok = true;
+        // clockwise from the anchor to a frontier outgoing half-edge (at the
+        // latest the boundary one: boundary edges are frontier edges)
+        int of = en.he;
+        for (int k = 0;; k++) {
+            if (is_frontier(d.tflag, of)) break;
+            const int g = twin[of];   // a non-frontier edge is interior
+            if (g < 0 || k > kRotGuard) {
+                ok = false;
+                break;
+            }
+            of = he_next(g);
+            if (of == en.he) {   // no frontier edge at x: not an end of a middle edge
+                ok = false;
+                break;
             }
         }
-        // past H steps clockwise: the last lane goes on alone (and finds the
-        // boundary if the turn reaches it there)
-        if (have && gl == H - 1) {
-            int f = e;
-            for (int steps = 0;; steps++) {
-                const int g = twin[f];
+        bool open = false;
+        if (ok) {   // counter-clockwise from of, round to of or to the boundary
+            int cur = of, o = of;
+            for (int k = 0;; k++) {
+                const int g = twin[he_prev(o)];
+                sweep_step(tfl, nxo, pvo, o, cur);
                 if (g < 0) {
-                    boundary = true;
+                    open = true;
                     break;
                 }
-                f = he_next(g);
-                if (f == o) break;
-                if (steps > kRotGuard) {
+                o = g;
+                if (o == of) break;
+                if (k > kRotGuard) {
                     ok = false;
                     break;
                 }
-                ok &= fix_around(d, f);
             }
         }
-        const bool open = (__ballot(boundary) & cwmask & gmask) != 0ull;
-        if (valid && gl >= H && open) {   // counter-clockwise: e <- twin(prev(e)), gl - H + 1 steps
-            have = true;
-            for (int s2 = 0; s2 <= gl - H; s2++) {
-                const int g = twin[he_prev(e)];
-                if (g < 0) {
-                    have = false;
-                    break;
-                }
-                e = g;
-            }
-        }
-        if (have) ok &= fix_around(d, e);
-        // past H steps counter-clockwise: the last lane goes on alone
-        if (have && gl == G - 1) {
-            for (int steps = 0;; steps++) {
-                const int g = twin[he_prev(e)];
+        if (ok && open && twin[of] >= 0) {   // the half-edges clockwise of of: from the clockwise end back to of
+            int ob = of;
+            for (int k = 0;; k++) {
+                const int g = twin[ob];
                 if (g < 0) break;
-                e = g;
-                if (steps > kRotGuard) {
+                ob = he_next(g);
+                if (k > kRotGuard) {
                     ok = false;
                     break;
                 }
-                ok &= fix_around(d, e);
+            }
+            int cur = ob, o = ob;
+            for (int k = 0; ok && o != of; k++) {
+                sweep_step(tfl, nxo, pvo, o, cur);
+                const int g = twin[he_prev(o)];
+                if (g < 0 || k > kRotGuard) {
+                    ok = false;
+                    break;
+                }
+                o = g;
             }
         }
-        if (valid && !ok) atomicOr(&d.ctr->err, kErrCorrupt);
+        if (!ok) atomicOr(&d.ctr->err, kErrCorrupt);
     }
 }
 
@@ -2314,8 +2266,7 @@ hipError_t launch_pipeline(const LaunchCfg &cfg, const RunBuffers &rb, hipStream
     H(K_REPAIR, 1);
 
     H(K_FIXUP, 0);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fixup<kFixLanes>), dim3(pb), dim3(pt), 0, s, rb.descs, rb.rc, rb.fixes,
-                       rb.cap_fix);
+    hipLaunchKernelGGL(k_fixup, dim3(pb), dim3(256), 0, s, rb.descs, rb.rc, rb.fixes, rb.cap_fix);
     H(K_FIXUP, 1);
 
     H(K_WALK, 0);
