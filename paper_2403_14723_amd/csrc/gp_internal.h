@@ -146,7 +146,8 @@ struct RunBuffers {
 // loops are left to k_emit
 constexpr int kWalkBuf = 16;
 constexpr int kWalkItems = 1;   // chains per k_walk thread
-constexpr int kScanChunk = 1024;   // compaction tiles per k_tile_scan block
+constexpr int kTileScanItems = 4;                   // compaction tiles per k_tile_scan thread
+constexpr int kScanChunk = 1024 * kTileScanItems;   // compaction tiles per k_tile_scan block
 // k_compact's LDS holds up to this many loop half-edges per 4 triangles of
 // its tile (2.75 per triangle; meshes average about 2 or fewer).  A tile
 // with more writes its loops straight to global memory.  With one seed and

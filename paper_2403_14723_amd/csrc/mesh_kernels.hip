@@ -1348,8 +1348,8 @@ __global__ void __launch_bounds__(256) k_emit(const MeshDesc *__restrict__ descs
 
 __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__ descs, uint64_t *status,
                                                      uint64_t *cpre, int cmp_tb) {
-    // block (mesh, chunk): tiles [chunk * kScanChunk, ...) of that mesh, one
-    // per thread, read and written contiguously
+    // block (mesh, chunk): tiles [chunk * kScanChunk, ...) of that mesh,
+    // kTileScanItems consecutive ones per thread, read and written contiguously
     __shared__ int s_scan[72];
     __shared__ int s_last;
     const MeshDesc &d = descs[blockIdx.x];
@@ -1357,12 +1357,37 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const MeshDesc *__restrict__
     const int nchunks = (ntiles + kScanChunk - 1) / kScanChunk;
     const int chunk = blockIdx.y;
     if (chunk >= nchunks) return;   // the whole block
-    const int tid = threadIdx.x, k = chunk * kScanChunk + tid;
+    const int tid = threadIdx.x, k0 = chunk * kScanChunk + tid * kTileScanItems;
     uint64_t *st = status + d.cmp_tile0;
-    const uint64_t v = k < ntiles ? st[k] : 0ull;
+    uint64_t v[kTileScanItems];
+    int lc = 0, lh = 0;
+#pragma unroll
+    for (int i = 0; i < kTileScanItems; i++) {
+        v[i] = k0 + i < ntiles ? st[k0 + i] : 0ull;
+        lc += (int)(v[i] >> 32);
+        lh += (int)(uint32_t)v[i];
+    }
     int ec, eh, tc, th;
-    block_excl_scan2((int)(v >> 32), (int)(uint32_t)v, ec, eh, tc, th, s_scan);
-    if (k < ntiles) st[k] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
+    block_excl_scan2(lc, lh, ec, eh, tc, th, s_scan);
+#pragma unroll
+    for (int i = 0; i < kTileScanItems; i++) {
+        if (k0 + i < ntiles) st[k0 + i] = ((uint64_t)(uint32_t)ec << 32) | (uint32_t)eh;
+        ec += (int)(v[i] >> 32);
+        eh += (int)(uint32_t)v[i];
+    }
+    if (nchunks == 1) {   // (uniform) the whole mesh in one block: its totals at once
+        if (tid == 0) {
+            cpre[d.cmp_tile0] = 0ull;
+            const bool ok = tc >= 0 && th >= 0 && tc <= d.nt && th <= 3 * d.nt;
+            d.ctr->npoly = ok ? tc : 0;
+            d.ctr->nloop = ok ? th : 0;
+            if (ok)
+                d.loop_off[tc] = th;
+            else
+                atomicOr(&d.ctr->err, kErrCorrupt);
+        }
+        return;
+    }
     // chunk total at the chunk's first tile; the last block of the mesh turns
     // the totals into prefixes
     if (tid == 0) {
