@@ -1104,11 +1104,12 @@ __device__ __forceinline__ int seek_frontier(const MeshDesc &d, int s) {
 // Every entry of the walk list: from the seed to a frontier half-edge of its
 // polygon (a frontier half-edge of the seed's own triangle if it has one),
 // around the loop, and the loop recorded.  A loop still open after
-// kWalkBoth steps is walked from both ends from then on: forward along
-// next' and backward along prev' from the start, the two loads of a step in
-// flight together, until the ends meet, so a long loop of len half-edges
-// takes about len / 2 dependent steps (short loops, the most, read no
-// prev').  Each
+// kWalkBoth steps (or after the first, when the loops are few and so
+// latency decides) is walked from both ends from then on:
+// forward along next' and backward along prev' from the start, the two
+// loads of a step in flight together, until the ends meet, so a long loop
+// of len half-edges takes about len / 2 dependent steps (short loops, the
+// most, read no prev').  Each
 // thread keeps ITEMS loops in flight and advances them in lock-step.  Every
 // chain also writes the half-edges it visits to an LDS buffer (forward ones
 // from the front, backward ones from the back), so the walker that claims a
@@ -1132,6 +1133,10 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
     const int nthreads = gridDim.x * blockDim.x;
     const int lane = __lane_id(), tid = threadIdx.x;
     const int wstripe = ((blockIdx.x * blockDim.x + tid) >> 6) % kStripes;   // this wave's pool stripe
+    // few loops (a quarter of the threads or fewer): every walk is its own
+    // critical path, so all go both ways from the first step; otherwise only
+    // the long ones
+    const int both = total <= nthreads / 4 ? 1 : kWalkBoth;
     for (int b0 = blockIdx.x * blockDim.x; b0 < total; b0 += nthreads * ITEMS) {   // block-uniform
         gcint nx[ITEMS], pv[ITEMS];
         // forward end fc (fa half-edges taken, from the start on), backward
@@ -1181,7 +1186,7 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                 closed[j] = false;
                 claim[j] = 0;
                 if (!live[j]) continue;
-                const bool two = fa[j] >= kWalkBoth;
+                const bool two = fa[j] >= both;
                 const int nf = nx[j][fc[j]], nb = two ? pv[j][bc[j]] : 0;
                 bool done = nf == bc[j];   // the forward end reached the backward one
                 if (!done && nf >= 0) {
