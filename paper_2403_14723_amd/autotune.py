@@ -55,9 +55,13 @@ def _spec(shapes: dict) -> str:
 
 
 def _parse(spec: str) -> dict:
+    """The "kernel=BxI" entries of a launch spec (other entries, such as
+    the small-mesh limit, are not tuned and are left as they are)."""
     out = {}
     for item in spec.split(","):
         k, v = item.split("=")
+        if "x" not in v:
+            continue
         b, i = v.split("x")
         out[k] = (int(b), int(i))
     return out

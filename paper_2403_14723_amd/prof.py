@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/mesh_kernels.hip", "csrc/gp_internal.h")
 MARK = "<!-- traffic:"
 # the meshing chain's kernels, in launch order
-CHAIN = ("k_label", "k_relink", "k_repair", "k_fixup", "k_walk", "k_tile_scan", "k_compact", "k_emit")
+CHAIN = ("k_label", "k_relink", "k_repair", "k_fixup", "k_walk", "k_tile_scan", "k_compact", "k_emit", "k_small")
 
 
 def sources_sha256() -> str:
