@@ -394,14 +394,18 @@ def bench_band(gp, W, stream, mesh, steps, nbands=8, band=3):
     return out
 
 
-def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lanes=4, loops_only=False):
-    """Continuous-batching server: capacity from a closed loop, then Poisson
-    arrivals at rho * capacity; latency = scheduled arrival -> result on the
-    host (the server stamps each request with its arrival time).  loops_only:
-    results carry seeds and loops, not next'/prev' (a third of the download).
-    The warm-up closed loop is as large as the capacity run, so that the server's
-    input pool already holds a buffer for every request in flight (a steady
-    state server's pool does)."""
+def bench_served(gp, W, n_req=2000, warm=512, cap_n=512, rhos=(0.5, 0.8), n_lanes=4, loops_only=False,
+                 clients=4):
+    """Continuous-batching server: capacity from a closed loop of `clients`
+    submitting threads (each submit copies its inputs, about 8 MB, into the
+    server's pinned memory, so one thread alone is bound by its own copies),
+    then Poisson arrivals at rho * capacity, submitted by as many threads in
+    turn; latency = scheduled arrival -> result on the host (the server
+    stamps each request with its arrival time).  loops_only: results carry
+    seeds and loops, not next'/prev' (a third of the download).  The warm-up
+    closed loop is as large as the capacity run, so that the server's input
+    pool already holds a buffer for every request in flight (a steady state
+    server's pool does)."""
     import queue
     import threading
     import numpy as np
@@ -411,16 +415,22 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lane
     srv = gp.Server(ctx, pool_bytes=48 << 30, max_batch=32, n_lanes=n_lanes, loops_only=loops_only)
 
     def closed_loop(n):
-        ts = [srv.submit(reqs[i % n_req].xy, reqs[i % n_req].tri) for i in range(n)]
-        for t in ts:
-            srv.wait(t).free()
+        def client(k):
+            ts = [srv.submit(reqs[i % n_req].xy, reqs[i % n_req].tri) for i in range(k, n, clients)]
+            for t in ts:
+                srv.wait(t).free()
+        th = [threading.Thread(target=client, args=(k,)) for k in range(clients)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
 
     closed_loop(warm)
     srv.reset_stats()
     closed_loop(cap_n)
     cap = srv.stats()["mtri_s"]
     out = {"requests": n_req, "mean_triangles": round(mean_t), "distinct_meshes": len({id(m) for m in reqs}),
-           "capacity_mtri_s": round(cap, 1), "lanes": n_lanes, "max_batch": 32,
+           "capacity_mtri_s": round(cap, 1), "capacity_clients": clients, "lanes": n_lanes, "max_batch": 32,
            "outputs": "seeds and loops" if loops_only else "next', prev', seeds and loops", "runs": []}
     for k, rho in enumerate(rhos):
         lam = rho * cap * 1e6 / mean_t
@@ -437,26 +447,36 @@ def bench_served(gp, W, n_req=2000, warm=256, cap_n=256, rhos=(0.5, 0.8), n_lane
 
         th = threading.Thread(target=waiter)
         th.start()
-        # arrivals on the monotonic clock the server stamps with: each
-        # request's latency runs from its scheduled arrival, so a submit that
-        # falls behind the schedule (or its input copy) is counted
-        at = time.monotonic_ns()
+        # arrivals on the monotonic clock the server stamps with, taken by
+        # `clients` submitting threads in turn (request i by thread i %
+        # clients): each request's latency runs from its scheduled arrival,
+        # so a submit that falls behind the schedule (or its input copy) is
+        # counted
+        t0 = time.monotonic_ns() + 2_000_000
+        at = t0 + np.cumsum((np.asarray(gaps[:n_req]) * 1e9).astype(np.int64))
         lags = np.empty(n_req)
-        first = last = 0
-        for i in range(n_req):
-            at += int(gaps[i] * 1e9)
-            d = (at - time.monotonic_ns()) * 1e-9
-            if d > 0:
-                time.sleep(d)
-            now = time.monotonic_ns()
-            lags[i] = (now - at) * 1e-6
-            first = now if i == 0 else first
-            last = now
-            tq.put(srv.submit(reqs[i].xy, reqs[i].tri, arrival_ns=at))
+        sub = np.empty(n_req, np.int64)
+
+        def arrivals(c):
+            for i in range(c, n_req, clients):
+                d = (int(at[i]) - time.monotonic_ns()) * 1e-9
+                if d > 0:
+                    time.sleep(d)
+                now = time.monotonic_ns()
+                lags[i] = (now - int(at[i])) * 1e-6
+                sub[i] = now
+                tq.put(srv.submit(reqs[i].xy, reqs[i].tri, arrival_ns=int(at[i])))
+
+        subs = [threading.Thread(target=arrivals, args=(c,)) for c in range(clients)]
+        for t in subs:
+            t.start()
+        for t in subs:
+            t.join()
+        first, last = int(sub.min()), int(sub.max())
         tq.put(None)
         th.join()
         st = srv.stats()
-        out["runs"].append({"rho": rho, "rate_per_s": round(lam, 1),
+        out["runs"].append({"rho": rho, "rate_per_s": round(lam, 1), "submitting_threads": clients,
                             "achieved_rate_per_s": round((n_req - 1) / ((last - first) * 1e-9), 1),
                             "max_lag_ms": round(float(lags.max()), 3), "mean_lag_ms": round(float(lags.mean()), 3),
                             "completed": st["completed"],
@@ -633,7 +653,7 @@ def main():
         served = bench_served(gp, W, n_req=args.served_requests)
         log(f"[bench] {served}")
         log("[bench] served, loops-only results")
-        served_loops = bench_served(gp, W, n_req=args.served_requests, n_lanes=6, loops_only=True)
+        served_loops = bench_served(gp, W, n_req=args.served_requests, n_lanes=8, loops_only=True)
         log(f"[bench] {served_loops}")
 
     cpu = None
