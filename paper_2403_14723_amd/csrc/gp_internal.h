@@ -197,6 +197,28 @@ inline int32_t tiles_for(int64_t n, int64_t tile) {
     return (int32_t)(k < 1 ? 1 : k);
 }
 
+// ---- small jobs: build and mesh in one workgroup (mesh_kernels.hip) -------
+//
+// A job of at most kJobSmallTri triangles and kJobSmallV vertices, its
+// inputs already on the device: one workgroup checks and orients it, matches
+// its twins in LDS, then meshes it as k_small does.  counts receives the
+// mesh counters (kJobCounts ints: the 8 of MeshCounters, the build's error
+// key as two words (~0 when the build passed), the triangles it flipped).
+constexpr int kJobSmallTri = kSmallMaxTri;
+constexpr int kJobSmallV = 4096;
+constexpr int kJobCounts = 12;
+struct SmallJob {
+    const int2 *xy;
+    const int32_t *tri;
+    int32_t nv, nt;
+    int32_t *org, *twin;   // device scratch, 3 nt each: the built structure
+    int32_t *next_o, *prev_o, *seeds, *loop_off, *loop_he;
+    int32_t *counts;
+};
+// dynamic LDS of one such workgroup
+size_t small_job_lds_bytes(int max_nv, int max_nt);
+hipError_t launch_small_jobs(const SmallJob *jobs, int n, int max_nv, int max_nt, hipStream_t s);
+
 // ---- build (build_kernels.hip) -------------------------------------------
 
 struct BuildBuffers {

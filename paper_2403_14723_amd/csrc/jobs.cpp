@@ -15,6 +15,7 @@
 // Memory goes back to the context's pool only after the host has seen the
 // downloads that read it complete, so the pool's reuse stays ordered.
 #include <algorithm>
+#include <cstring>
 #include <deque>
 #include <vector>
 
@@ -94,6 +95,143 @@ void group_finish(Group &g, hipStream_t cs) {
     group_free(g);
 }
 
+// ---- small jobs: packed copies, one build-and-mesh launch per group -------
+//
+// A list whose jobs all fit one workgroup (gp::kJobSmallTri triangles,
+// gp::kJobSmallV vertices) is not worth a build and a batched run per group:
+// the dozen runtime calls per job that those take would bound it.  Each
+// group's inputs are packed into one pinned staging block and uploaded with
+// one copy; one launch builds and meshes every job (k_small_jobs); one copy
+// brings every output back, and the host hands each job its part.
+
+bool small_jobs_fit(const gp_ctx *c, const gp_job *jobs, int n) {
+    int max_nv = 0, max_nt = 0;
+    for (int i = 0; i < n; i++) {
+        if (jobs[i].nt > gp::kJobSmallTri || jobs[i].nv > gp::kJobSmallV) return false;
+        max_nv = std::max(max_nv, jobs[i].nv);
+        max_nt = std::max(max_nt, jobs[i].nt);
+    }
+    return c->cfg.small_max >= max_nt && gp::small_job_lds_bytes(max_nv, max_nt) <= (size_t)c->cfg.lds_max;
+}
+
+// Byte offsets of one job's parts: inputs (xy, tri) in the upload block;
+// structure scratch (org, twin) and outputs (counts, next, prev, seeds,
+// loop_off, loop_he) in the device block, outputs contiguous per group.
+struct SmallLayout {
+    size_t xy, tri, org, twin, counts, next, prev, seeds, loop_off, loop_he;
+};
+
+int run_small_group(gp_ctx *c, gp_job *jobs, int j0, int j1) {
+    const int n = j1 - j0;
+    std::vector<SmallLayout> lay(n);
+    size_t in_bytes = 0, scratch_bytes = 0, out_bytes = 0;
+    int max_nv = 0, max_nt = 0;
+    for (int k = 0; k < n; k++) {
+        const gp_job &jb = jobs[j0 + k];
+        const size_t nh = 3 * (size_t)jb.nt;
+        SmallLayout &L = lay[k];
+        L.xy = in_bytes;
+        in_bytes += align_up(8 * (size_t)jb.nv, 16);
+        L.tri = in_bytes;
+        in_bytes += align_up(12 * (size_t)jb.nt, 16);
+        L.org = scratch_bytes;
+        scratch_bytes += align_up(4 * nh + 4, 16);
+        L.twin = scratch_bytes;
+        scratch_bytes += align_up(4 * nh + 4, 16);
+        L.counts = out_bytes;
+        out_bytes += align_up(4 * (size_t)gp::kJobCounts, 16);
+        L.next = out_bytes;
+        out_bytes += align_up(4 * nh + 4, 16);
+        L.prev = out_bytes;
+        out_bytes += align_up(4 * nh + 4, 16);
+        L.seeds = out_bytes;
+        out_bytes += align_up(4 * (size_t)jb.nt + 4, 16);
+        L.loop_off = out_bytes;
+        out_bytes += align_up(4 * (size_t)jb.nt + 8, 16);
+        L.loop_he = out_bytes;
+        out_bytes += align_up(4 * nh + 4, 16);
+        max_nv = std::max(max_nv, jb.nv);
+        max_nt = std::max(max_nt, jb.nt);
+    }
+    const size_t desc_off = align_up(in_bytes, 256);
+    const size_t up_bytes = desc_off + sizeof(gp::SmallJob) * (size_t)n;   // inputs, then descriptors
+    const size_t scratch_off = align_up(up_bytes, 256), out_off = align_up(scratch_off + scratch_bytes, 256);
+    const size_t dev_bytes = out_off + out_bytes;
+    void *dev = nullptr;
+    int rc = c->pool.alloc(dev_bytes, &dev);
+    if (rc != GP_OK) return rc;
+    char *up = static_cast<char *>(pinned_take(c, up_bytes));
+    char *down = static_cast<char *>(pinned_take(c, out_bytes));
+    if (!up || !down) {
+        if (up) pinned_give(c, up, up_bytes);
+        if (down) pinned_give(c, down, out_bytes);
+        c->pool.release(dev);
+        return GP_ENOMEM;
+    }
+    char *d = static_cast<char *>(dev);
+    gp::SmallJob *descs = reinterpret_cast<gp::SmallJob *>(up + desc_off);
+    for (int k = 0; k < n; k++) {
+        const gp_job &jb = jobs[j0 + k];
+        const SmallLayout &L = lay[k];
+        if (jb.nv) std::memcpy(up + L.xy, jb.xy, 8 * (size_t)jb.nv);
+        if (jb.nt) std::memcpy(up + L.tri, jb.tri, 12 * (size_t)jb.nt);
+        gp::SmallJob &sj = descs[k];
+        sj.xy = reinterpret_cast<const int2 *>(d + L.xy);
+        sj.tri = reinterpret_cast<const int32_t *>(d + L.tri);
+        sj.nv = jb.nv;
+        sj.nt = jb.nt;
+        sj.org = reinterpret_cast<int32_t *>(d + scratch_off + L.org);
+        sj.twin = reinterpret_cast<int32_t *>(d + scratch_off + L.twin);
+        sj.counts = reinterpret_cast<int32_t *>(d + out_off + L.counts);
+        sj.next_o = reinterpret_cast<int32_t *>(d + out_off + L.next);
+        sj.prev_o = reinterpret_cast<int32_t *>(d + out_off + L.prev);
+        sj.seeds = reinterpret_cast<int32_t *>(d + out_off + L.seeds);
+        sj.loop_off = reinterpret_cast<int32_t *>(d + out_off + L.loop_off);
+        sj.loop_he = reinterpret_cast<int32_t *>(d + out_off + L.loop_he);
+    }
+    hipStream_t s = c->stream;
+    if (hipMemcpyAsync(d, up, up_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        gp::launch_small_jobs(reinterpret_cast<const gp::SmallJob *>(d + desc_off), n, max_nv, max_nt, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(down, d + out_off, out_bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        rc = GP_EHIP;
+    }
+    for (int k = 0; k < n && rc == GP_OK; k++) {
+        gp_job &jb = jobs[j0 + k];
+        const SmallLayout &L = lay[k];
+        const int32_t *cnt = reinterpret_cast<const int32_t *>(down + L.counts);
+        const uint64_t key = (uint64_t)(uint32_t)cnt[8] | ((uint64_t)(uint32_t)cnt[9] << 32);
+        gp::MeshCounters mc;
+        std::memcpy(&mc, cnt, sizeof mc);
+        if (key != ~0ull) {
+            jb.status = -(int)(key & 0xff);
+            continue;
+        }
+        if (mc.err || mc.npoly < 0 || mc.npoly > jb.nt || mc.nloop < 0 || mc.nloop > 3 * jb.nt) {
+            jb.status = GP_ECORRUPT;
+            continue;
+        }
+        const size_t nh = 3 * (size_t)jb.nt;
+        jb.npoly = mc.npoly;
+        jb.nloop_he = mc.nloop;
+        if (jb.next && nh) std::memcpy(jb.next, down + L.next, 4 * nh);
+        if (jb.prev && nh) std::memcpy(jb.prev, down + L.prev, 4 * nh);
+        if (mc.npoly) std::memcpy(jb.seeds, down + L.seeds, 4 * (size_t)mc.npoly);
+        std::memcpy(jb.loop_off, down + L.loop_off, 4 * ((size_t)mc.npoly + 1));
+        if (mc.nloop) std::memcpy(jb.loop_he, down + L.loop_he, 4 * (size_t)mc.nloop);
+        jb.status = GP_OK;
+    }
+    if (rc != GP_OK)
+        for (int k = 0; k < n; k++) jobs[j0 + k].status = rc;
+    pinned_give(c, up, up_bytes);
+    pinned_give(c, down, out_bytes);
+    c->pool.release(dev);   // the stream has drained
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -115,6 +253,20 @@ int gpolylla_mesh_jobs(gp_ctx *c, gp_job *jobs, int32_t n, int64_t group_triangl
     if (n == 0) return GP_OK;
     const int64_t budget = group_triangles > 0 ? group_triangles : ((int64_t)8 << 20);
     DeviceGuard dg(c->device);
+    if (small_jobs_fit(c, jobs, n)) {   // every job builds and meshes in one workgroup
+        int rc_all = GP_OK;
+        for (int j0 = 0; j0 < n;) {
+            int j1 = j0;
+            int64_t tri = 0;
+            while (j1 < n && j1 - j0 < 65535 && (j1 == j0 || tri + jobs[j1].nt <= budget)) tri += jobs[j1++].nt;
+            const int rc = run_small_group(c, jobs, j0, j1);
+            if (rc != GP_OK && rc_all == GP_OK) rc_all = rc;
+            j0 = j1;
+        }
+        for (int i = 0; i < n; i++)
+            if (jobs[i].status != GP_OK && rc_all == GP_OK) rc_all = jobs[i].status;
+        return rc_all;
+    }
     hipStream_t us = nullptr, cs = nullptr;   // uploads, downloads
     if (hipStreamCreateWithFlags(&us, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {

@@ -2126,6 +2126,179 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_one(const MeshDesc d, Mes
 }
 
 // ---------------------------------------------------------------------------
+// k_small_jobs: build and mesh one small job per workgroup
+//
+// The half-edge build of Section 4.1-4.2 for a job small enough for LDS, in
+// the order and with the error reports of the staged build kernels: every
+// coordinate in [0, 2^30]; every corner index in [0, nv) and no zero-area
+// triangle (exact int64 orientation test), clockwise triangles reordered
+// counter-clockwise; then twins by bucketing the half-edges by origin and
+// searching the target's bucket for the reverse edge, where two reverse
+// edges, or a repeated directed edge without one, is non-manifold.  Errors
+// keep the lowest (rank << 8 | code): coordinates first, then the lowest bad
+// triangle, then the lowest non-manifold half-edge; the twins are matched
+// only when the first checks pass.  The built structure goes to device
+// scratch and the workgroup then meshes it as k_small does.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long job_key(unsigned long long rank, int code) {
+    return (rank << 8) | (unsigned long long)(-code);
+}
+
+size_t small_job_lds_bytes(int max_nv, int max_nt) {
+    // corners (3 nt), bucket starts (nv + 1), fill cursors (nv), bucket (3 nt)
+    const size_t build = 4 * (3 * (size_t)max_nt + (size_t)max_nv + 1 + (size_t)max_nv + 3 * (size_t)max_nt) + 64;
+    const size_t mesh = small_lds_bytes(max_nt);
+    return build > mesh ? build : mesh;
+}
+
+template <int IT>
+__global__ void __launch_bounds__(kSmallBlock) k_small_jobs(const SmallJob *__restrict__ jobs) {
+    extern __shared__ int4 lds_raw[];
+    __shared__ unsigned long long s_key;
+    __shared__ int s_flip;
+    __shared__ int s_scan[72];
+    const SmallJob &jd = jobs[blockIdx.x];
+    const int nv = jd.nv, nt = jd.nt, nh = 3 * nt, tid = threadIdx.x;
+    if (tid == 0) {
+        s_key = ~0ull;
+        s_flip = 0;
+    }
+    if (nv < 0 || nt < 0 || nv > kJobSmallV || nt > (IT / 3) * kSmallBlock) {   // (uniform) never launched so
+        if (tid == 0) {
+            jd.counts[8] = (int)(uint32_t)job_key(0, -1);
+            jd.counts[9] = 0;
+        }
+        return;
+    }
+    int *s_org = reinterpret_cast<int *>(lds_raw);   // 3 nt corners, counter-clockwise
+    int *s_vst = s_org + nh;                          // nv + 1 bucket starts
+    int *s_cur = s_vst + nv + 1;                      // nv fill cursors
+    int *s_bkt = s_cur + nv;                          // nh half-edges grouped by origin
+    __syncthreads();
+    // coordinates
+    for (int v = tid; v < nv; v += kSmallBlock) {
+        const int2 p = jd.xy[v];
+        if (p.x < 0 || p.x > (1 << 30) || p.y < 0 || p.y > (1 << 30)) atomicMin(&s_key, job_key(0, -2));
+    }
+    // corners: indices, orientation, counter-clockwise order
+    int flips = 0;
+    for (int t = tid; t < nt; t += kSmallBlock) {
+        int a = jd.tri[3 * t], b = jd.tri[3 * t + 1], c = jd.tri[3 * t + 2];
+        if ((unsigned)a >= (unsigned)nv || (unsigned)b >= (unsigned)nv || (unsigned)c >= (unsigned)nv) {
+            atomicMin(&s_key, job_key(1ull + t, -1));
+            a = b = c = 0;
+        } else {
+            const int2 pa = jd.xy[a], pb = jd.xy[b], pc = jd.xy[c];
+            const long long o = ((long long)pb.x - pa.x) * ((long long)pc.y - pa.y) -
+                                ((long long)pb.y - pa.y) * ((long long)pc.x - pa.x);
+            if (o == 0) {
+                atomicMin(&s_key, job_key(1ull + t, -3));
+            } else if (o < 0) {
+                const int sw = b;
+                b = c;
+                c = sw;
+                flips++;
+            }
+        }
+        s_org[3 * t] = a;
+        s_org[3 * t + 1] = b;
+        s_org[3 * t + 2] = c;
+    }
+    if (flips) atomicAdd(&s_flip, flips);
+    for (int v = tid; v <= nv; v += kSmallBlock) s_vst[v] = 0;
+    __syncthreads();
+    if (s_key != ~0ull) {   // (uniform) the inputs failed their checks: no twins
+        if (tid == 0) {
+            jd.counts[8] = (int)(uint32_t)s_key;
+            jd.counts[9] = (int)(uint32_t)(s_key >> 32);
+        }
+        return;
+    }
+    // out-degrees, their exclusive scan (four vertices per thread), buckets
+    for (int h = tid; h < nh; h += kSmallBlock) atomicAdd(&s_vst[s_org[h]], 1);
+    __syncthreads();
+    {
+        constexpr int VP = (kJobSmallV + kSmallBlock - 1) / kSmallBlock;
+        const int v0 = tid * VP;
+        int dv[VP], sum = 0;
+#pragma unroll
+        for (int k = 0; k < VP; k++) {
+            dv[k] = v0 + k < nv ? s_vst[v0 + k] : 0;
+            sum += dv[k];
+        }
+        int ex, ex2, tot, tot2;
+        block_excl_scan2(sum, 0, ex, ex2, tot, tot2, s_scan);
+#pragma unroll
+        for (int k = 0; k < VP; k++) {
+            if (v0 + k < nv) {
+                s_vst[v0 + k] = ex;
+                s_cur[v0 + k] = ex;
+            }
+            ex += dv[k];
+        }
+        if (tid == 0) s_vst[nv] = tot;
+    }
+    __syncthreads();
+    for (int h = tid; h < nh; h += kSmallBlock) s_bkt[atomicAdd(&s_cur[s_org[h]], 1)] = h;
+    __syncthreads();
+    // twins: h = u->v pairs with the one v->u in v's bucket
+    for (int h = tid; h < nh; h += kSmallBlock) {
+        const int u = s_org[h], v = s_org[he_next(h)];
+        int found = -1, nrev = 0, ndup = 0;
+        for (int k = s_vst[v], e = s_vst[v + 1]; k < e; k++) {
+            const int g = s_bkt[k];
+            if (s_org[he_next(g)] == u) {
+                found = g;
+                ++nrev;
+            }
+        }
+        if (nrev == 0)
+            for (int k = s_vst[u], e = s_vst[u + 1]; k < e; k++) {
+                const int g = s_bkt[k];
+                if (g != h && s_org[he_next(g)] == v) ++ndup;
+            }
+        if (nrev > 1 || ndup > 0) atomicMin(&s_key, job_key(1ull + nt + h, -4));
+        jd.org[h] = u;
+        jd.twin[h] = nrev == 1 ? found : -1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        jd.counts[8] = (int)(uint32_t)s_key;
+        jd.counts[9] = (int)(uint32_t)(s_key >> 32);
+        jd.counts[10] = s_flip;
+    }
+    if (s_key != ~0ull) return;   // (uniform)
+    __threadfence_block();   // the structure in global memory, for the meshing that follows
+    MeshDesc d{};
+    d.xy = jd.xy;
+    d.org = jd.org;
+    d.twin = jd.twin;
+    d.next_o = jd.next_o;
+    d.prev_o = jd.prev_o;
+    d.seeds = jd.seeds;
+    d.loop_off = jd.loop_off;
+    d.loop_he = jd.loop_he;
+    d.ctr = reinterpret_cast<MeshCounters *>(jd.counts);
+    d.nt = nt;
+    d.nv = nv;
+    small_body<IT>(d, nullptr);
+}
+
+hipError_t launch_small_jobs(const SmallJob *jobs, int n, int max_nv, int max_nt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(n), block(kSmallBlock);
+    const size_t lds = small_job_lds_bytes(max_nv, max_nt);
+    if (max_nt <= kSmallBlock)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_jobs<3>), grid, block, lds, s, jobs);
+    else if (max_nt <= 2 * kSmallBlock)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_jobs<6>), grid, block, lds, s, jobs);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_small_jobs<12>), grid, block, lds, s, jobs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // small copies between device memory and coherent pinned host memory (the
 // descriptor table before a run, the per-mesh counters after it): a kernel
 // in stream order instead of the runtime's copy path
@@ -2224,12 +2397,15 @@ hipError_t launch_small_one(const MeshDesc &d, MeshCounters *host, hipStream_t s
 }
 
 int prepare_small(int lds_block) {
-    const void *const fns[6] = {reinterpret_cast<const void *>(&k_small<3>),
+    const void *const fns[9] = {reinterpret_cast<const void *>(&k_small<3>),
                                 reinterpret_cast<const void *>(&k_small<6>),
                                 reinterpret_cast<const void *>(&k_small<12>),
                                 reinterpret_cast<const void *>(&k_small_one<3>),
                                 reinterpret_cast<const void *>(&k_small_one<6>),
-                                reinterpret_cast<const void *>(&k_small_one<12>)};
+                                reinterpret_cast<const void *>(&k_small_one<12>),
+                                reinterpret_cast<const void *>(&k_small_jobs<3>),
+                                reinterpret_cast<const void *>(&k_small_jobs<6>),
+                                reinterpret_cast<const void *>(&k_small_jobs<12>)};
     int fixed = 0;
     for (const void *f : fns) {
         hipFuncAttributes a{};

@@ -18,6 +18,31 @@
 
 using namespace gprt;
 
+namespace gprt {
+
+void *pinned_take(gp_ctx *c, size_t n) {
+    n = align_up(n ? n : kAlign);
+    auto it = c->pinned_free.lower_bound(n);
+    if (it != c->pinned_free.end() && it->first <= 2 * n) {
+        void *p = it->second;
+        c->pinned_free.erase(it);
+        return p;
+    }
+    void *p = nullptr;
+    // coherent: the device writes the run counters here with a kernel
+    if (hipHostMalloc(&p, n, hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void pinned_give(gp_ctx *c, void *p, size_t n) {
+    if (p) c->pinned_free.emplace(align_up(n ? n : kAlign), p);
+}
+
+}  // namespace gprt
+
 namespace {
 
 #define HIP_OK(expr)                                        \
@@ -114,27 +139,6 @@ void resolve_profile(gp_ctx *c) {
         c->spare_events.push_back(p.b);
     }
     c->pending.resize(k);
-}
-
-void *pinned_take(gp_ctx *c, size_t n) {
-    n = align_up(n ? n : kAlign);
-    auto it = c->pinned_free.lower_bound(n);
-    if (it != c->pinned_free.end() && it->first <= 2 * n) {
-        void *p = it->second;
-        c->pinned_free.erase(it);
-        return p;
-    }
-    void *p = nullptr;
-    // coherent: the device writes the run counters here with a kernel
-    if (hipHostMalloc(&p, n, hipHostMallocCoherent) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    return p;
-}
-
-void pinned_give(gp_ctx *c, void *p, size_t n) {
-    if (p) c->pinned_free.emplace(align_up(n ? n : kAlign), p);
 }
 
 // Copies host bytes to device memory through a pinned staging slot, read by a

@@ -155,6 +155,11 @@ struct DeviceGuard {
 // each) with two host checks in all, on the context's stream: out[i] and
 // status[i] per build.  Returns GP_ENOMEM when the host staging cannot be
 // allocated (nothing built), else GP_OK.
+// Coherent pinned host blocks cached per context (a block of at least n
+// bytes, reused when it is at most twice that; give back with its size).
+void *pinned_take(gp_ctx *c, size_t n);
+void pinned_give(gp_ctx *c, void *p, size_t n);
+
 int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
                const int32_t *nt, uint32_t flags, gp_mesh **out, int *status);
 
