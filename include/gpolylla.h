@@ -305,6 +305,12 @@ typedef struct {
  * Meshes jobs[0..n) in order.  Consecutive jobs are grouped up to
  * group_triangles triangles (0: 8M; a larger job is a group of its own) and
  * each group is one batched run (gpolylla_mesh_batch); flags: 0 or GP_GRAPH.
+ * A list whose jobs all have at most 4096 triangles and 4096 vertices (and
+ * fit the device's LDS per workgroup) runs packed instead: per group one
+ * upload of every job's inputs from a pinned staging block, one launch that
+ * builds and meshes each job in a workgroup of its own (the same checks and
+ * error codes as gpolylla_build_halfedges), and one download; flags are
+ * then ignored.
  * Uses the context's stream for uploads, builds and runs, and a stream of its
  * own for the downloads; returns when every job's outputs are in host memory.
  * Returns GP_OK when every job succeeded, else the first failed job's status
