@@ -121,15 +121,27 @@ struct SmallLayout {
     size_t xy, tri, org, twin, counts, next, prev, seeds, loop_off, loop_he;
 };
 
-int run_small_group(gp_ctx *c, gp_job *jobs, int j0, int j1) {
-    const int n = j1 - j0;
-    std::vector<SmallLayout> lay(n);
+// One packed group in flight: its layout, staging blocks and device block.
+struct SmallGroup {
+    int j0 = 0, j1 = 0;
+    std::vector<SmallLayout> lay;
+    char *up = nullptr, *down = nullptr;
+    size_t up_bytes = 0, out_bytes = 0;
+    void *dev = nullptr;
+    hipEvent_t done = nullptr;
+    int rc = GP_OK;
+};
+
+// Packs jobs [j0, j1) and queues their upload, the launch and the download.
+void small_group_start(gp_ctx *c, gp_job *jobs, SmallGroup &g) {
+    const int n = g.j1 - g.j0;
+    g.lay.assign(n, SmallLayout{});
     size_t in_bytes = 0, scratch_bytes = 0, out_bytes = 0;
     int max_nv = 0, max_nt = 0;
     for (int k = 0; k < n; k++) {
-        const gp_job &jb = jobs[j0 + k];
+        const gp_job &jb = jobs[g.j0 + k];
         const size_t nh = 3 * (size_t)jb.nt;
-        SmallLayout &L = lay[k];
+        SmallLayout &L = g.lay[k];
         L.xy = in_bytes;
         in_bytes += align_up(8 * (size_t)jb.nv, 16);
         L.tri = in_bytes;
@@ -154,27 +166,25 @@ int run_small_group(gp_ctx *c, gp_job *jobs, int j0, int j1) {
         max_nt = std::max(max_nt, jb.nt);
     }
     const size_t desc_off = align_up(in_bytes, 256);
-    const size_t up_bytes = desc_off + sizeof(gp::SmallJob) * (size_t)n;   // inputs, then descriptors
-    const size_t scratch_off = align_up(up_bytes, 256), out_off = align_up(scratch_off + scratch_bytes, 256);
-    const size_t dev_bytes = out_off + out_bytes;
-    void *dev = nullptr;
-    int rc = c->pool.alloc(dev_bytes, &dev);
-    if (rc != GP_OK) return rc;
-    char *up = static_cast<char *>(pinned_take(c, up_bytes));
-    char *down = static_cast<char *>(pinned_take(c, out_bytes));
-    if (!up || !down) {
-        if (up) pinned_give(c, up, up_bytes);
-        if (down) pinned_give(c, down, out_bytes);
-        c->pool.release(dev);
-        return GP_ENOMEM;
+    g.up_bytes = desc_off + sizeof(gp::SmallJob) * (size_t)n;   // inputs, then descriptors
+    g.out_bytes = out_bytes;
+    const size_t scratch_off = align_up(g.up_bytes, 256), out_off = align_up(scratch_off + scratch_bytes, 256);
+    g.rc = c->pool.alloc(out_off + out_bytes, &g.dev);
+    if (g.rc != GP_OK) return;
+    g.up = static_cast<char *>(pinned_take(c, g.up_bytes));
+    g.down = static_cast<char *>(pinned_take(c, g.out_bytes));
+    if (!g.up || !g.down || hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        g.rc = GP_ENOMEM;
+        return;
     }
-    char *d = static_cast<char *>(dev);
-    gp::SmallJob *descs = reinterpret_cast<gp::SmallJob *>(up + desc_off);
+    char *d = static_cast<char *>(g.dev);
+    gp::SmallJob *descs = reinterpret_cast<gp::SmallJob *>(g.up + desc_off);
     for (int k = 0; k < n; k++) {
-        const gp_job &jb = jobs[j0 + k];
-        const SmallLayout &L = lay[k];
-        if (jb.nv) std::memcpy(up + L.xy, jb.xy, 8 * (size_t)jb.nv);
-        if (jb.nt) std::memcpy(up + L.tri, jb.tri, 12 * (size_t)jb.nt);
+        const gp_job &jb = jobs[g.j0 + k];
+        const SmallLayout &L = g.lay[k];
+        if (jb.nv) std::memcpy(g.up + L.xy, jb.xy, 8 * (size_t)jb.nv);
+        if (jb.nt) std::memcpy(g.up + L.tri, jb.tri, 12 * (size_t)jb.nt);
         gp::SmallJob &sj = descs[k];
         sj.xy = reinterpret_cast<const int2 *>(d + L.xy);
         sj.tri = reinterpret_cast<const int32_t *>(d + L.tri);
@@ -190,19 +200,28 @@ int run_small_group(gp_ctx *c, gp_job *jobs, int j0, int j1) {
         sj.loop_he = reinterpret_cast<int32_t *>(d + out_off + L.loop_he);
     }
     hipStream_t s = c->stream;
-    if (hipMemcpyAsync(d, up, up_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(d, g.up, g.up_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
         gp::launch_small_jobs(reinterpret_cast<const gp::SmallJob *>(d + desc_off), n, max_nv, max_nt, s) !=
             hipSuccess ||
-        hipMemcpyAsync(down, d + out_off, out_bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+        hipMemcpyAsync(g.down, d + out_off, g.out_bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(g.done, s) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipStreamSynchronize(s);
-        rc = GP_EHIP;
+        g.rc = GP_EHIP;
     }
-    for (int k = 0; k < n && rc == GP_OK; k++) {
-        gp_job &jb = jobs[j0 + k];
-        const SmallLayout &L = lay[k];
-        const int32_t *cnt = reinterpret_cast<const int32_t *>(down + L.counts);
+}
+
+// Waits for a started group, hands each job its outputs and status, and
+// gives the group's memory back.
+void small_group_finish(gp_ctx *c, gp_job *jobs, SmallGroup &g) {
+    if (g.rc == GP_OK && hipEventSynchronize(g.done) != hipSuccess) {
+        (void)hipGetLastError();
+        g.rc = GP_EHIP;
+    }
+    if (g.rc != GP_OK) (void)hipStreamSynchronize(c->stream);   // nothing may still read or write the blocks
+    for (int k = 0; k < g.j1 - g.j0 && g.rc == GP_OK; k++) {
+        gp_job &jb = jobs[g.j0 + k];
+        const SmallLayout &L = g.lay[k];
+        const int32_t *cnt = reinterpret_cast<const int32_t *>(g.down + L.counts);
         const uint64_t key = (uint64_t)(uint32_t)cnt[8] | ((uint64_t)(uint32_t)cnt[9] << 32);
         gp::MeshCounters mc;
         std::memcpy(&mc, cnt, sizeof mc);
@@ -217,19 +236,20 @@ int run_small_group(gp_ctx *c, gp_job *jobs, int j0, int j1) {
         const size_t nh = 3 * (size_t)jb.nt;
         jb.npoly = mc.npoly;
         jb.nloop_he = mc.nloop;
-        if (jb.next && nh) std::memcpy(jb.next, down + L.next, 4 * nh);
-        if (jb.prev && nh) std::memcpy(jb.prev, down + L.prev, 4 * nh);
-        if (mc.npoly) std::memcpy(jb.seeds, down + L.seeds, 4 * (size_t)mc.npoly);
-        std::memcpy(jb.loop_off, down + L.loop_off, 4 * ((size_t)mc.npoly + 1));
-        if (mc.nloop) std::memcpy(jb.loop_he, down + L.loop_he, 4 * (size_t)mc.nloop);
+        if (jb.next && nh) std::memcpy(jb.next, g.down + L.next, 4 * nh);
+        if (jb.prev && nh) std::memcpy(jb.prev, g.down + L.prev, 4 * nh);
+        if (mc.npoly) std::memcpy(jb.seeds, g.down + L.seeds, 4 * (size_t)mc.npoly);
+        std::memcpy(jb.loop_off, g.down + L.loop_off, 4 * ((size_t)mc.npoly + 1));
+        if (mc.nloop) std::memcpy(jb.loop_he, g.down + L.loop_he, 4 * (size_t)mc.nloop);
         jb.status = GP_OK;
     }
-    if (rc != GP_OK)
-        for (int k = 0; k < n; k++) jobs[j0 + k].status = rc;
-    pinned_give(c, up, up_bytes);
-    pinned_give(c, down, out_bytes);
-    c->pool.release(dev);   // the stream has drained
-    return rc;
+    if (g.rc != GP_OK)
+        for (int k = g.j0; k < g.j1; k++) jobs[k].status = g.rc;
+    if (g.up) pinned_give(c, g.up, g.up_bytes);
+    if (g.down) pinned_give(c, g.down, g.out_bytes);
+    if (g.dev) c->pool.release(g.dev);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g = SmallGroup{};
 }
 
 }  // namespace
@@ -254,15 +274,28 @@ int gpolylla_mesh_jobs(gp_ctx *c, gp_job *jobs, int32_t n, int64_t group_triangl
     const int64_t budget = group_triangles > 0 ? group_triangles : ((int64_t)8 << 20);
     DeviceGuard dg(c->device);
     if (small_jobs_fit(c, jobs, n)) {   // every job builds and meshes in one workgroup
-        int rc_all = GP_OK;
-        for (int j0 = 0; j0 < n;) {
-            int j1 = j0;
+        // two groups in flight: the host packs the next while the device
+        // works on the current one, and unpacks it while the next runs
+        SmallGroup cur, nxt;
+        int j0 = 0;
+        auto form = [&](SmallGroup &g) {
             int64_t tri = 0;
-            while (j1 < n && j1 - j0 < 65535 && (j1 == j0 || tri + jobs[j1].nt <= budget)) tri += jobs[j1++].nt;
-            const int rc = run_small_group(c, jobs, j0, j1);
-            if (rc != GP_OK && rc_all == GP_OK) rc_all = rc;
-            j0 = j1;
+            g.j0 = g.j1 = j0;
+            while (g.j1 < n && g.j1 - g.j0 < 65535 && (g.j1 == g.j0 || tri + jobs[g.j1].nt <= budget))
+                tri += jobs[g.j1++].nt;
+            j0 = g.j1;
+            small_group_start(c, jobs, g);
+        };
+        form(cur);
+        while (true) {
+            const bool more = j0 < n;
+            if (more) form(nxt);
+            small_group_finish(c, jobs, cur);
+            if (!more) break;
+            cur = std::move(nxt);
+            nxt = SmallGroup{};
         }
+        int rc_all = GP_OK;
         for (int i = 0; i < n; i++)
             if (jobs[i].status != GP_OK && rc_all == GP_OK) rc_all = jobs[i].status;
         return rc_all;
