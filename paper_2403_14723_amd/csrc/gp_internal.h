@@ -211,9 +211,12 @@ struct SmallJob {
     const int2 *xy;
     const int32_t *tri;
     int32_t nv, nt;
-    int32_t *org, *twin;   // device scratch, 3 nt each: the built structure
+    int32_t *org, *twin;   // 3 nt each: the built structure
     int32_t *next_o, *prev_o, *seeds, *loop_off, *loop_he;
     int32_t *counts;
+    int2 *xy_out;          // when set, xy is copied here (the built mesh's own coordinates)
+    int32_t build_only;    // 1: stop after the build (a mesh for later runs)
+    int32_t pad;
 };
 // dynamic LDS of one such workgroup
 size_t small_job_lds_bytes(int max_nv, int max_nt);

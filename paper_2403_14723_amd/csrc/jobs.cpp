@@ -198,6 +198,9 @@ void small_group_start(gp_ctx *c, gp_job *jobs, SmallGroup &g) {
         sj.seeds = reinterpret_cast<int32_t *>(d + out_off + L.seeds);
         sj.loop_off = reinterpret_cast<int32_t *>(d + out_off + L.loop_off);
         sj.loop_he = reinterpret_cast<int32_t *>(d + out_off + L.loop_he);
+        sj.xy_out = nullptr;
+        sj.build_only = 0;
+        sj.pad = 0;
     }
     hipStream_t s = c->stream;
     if (hipMemcpyAsync(d, g.up, g.up_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -2176,9 +2176,10 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_jobs(const SmallJob *__re
     int *s_cur = s_vst + nv + 1;                      // nv fill cursors
     int *s_bkt = s_cur + nv;                          // nh half-edges grouped by origin
     __syncthreads();
-    // coordinates
+    // coordinates (and the mesh's own copy of them)
     for (int v = tid; v < nv; v += kSmallBlock) {
         const int2 p = jd.xy[v];
+        if (jd.xy_out) jd.xy_out[v] = p;
         if (p.x < 0 || p.x > (1 << 30) || p.y < 0 || p.y > (1 << 30)) atomicMin(&s_key, job_key(0, -2));
     }
     // corners: indices, orientation, counter-clockwise order
@@ -2268,7 +2269,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_small_jobs(const SmallJob *__re
         jd.counts[9] = (int)(uint32_t)(s_key >> 32);
         jd.counts[10] = s_flip;
     }
-    if (s_key != ~0ull) return;   // (uniform)
+    if (s_key != ~0ull || jd.build_only) return;   // (uniform)
     __threadfence_block();   // the structure in global memory, for the meshing that follows
     MeshDesc d{};
     d.xy = jd.xy;

@@ -612,8 +612,137 @@ int renumber_input(gp_ctx *c, const int32_t *xy, int32_t nv, const int32_t *tri,
 
 }  // namespace
 
+// Builds meshes that each fit one workgroup with one launch of the small-job
+// kernel in build-only mode: host inputs packed into one upload, the checks,
+// orientation and twin matching in LDS (with the staged build's error codes
+// and ranking), and one download of every mesh's error key and flip count.
+int build_small_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
+                     const int32_t *nt, uint32_t flags, gp_mesh **out, int *status) {
+    const bool in_dev = (flags & GP_IN_DEVICE) != 0;
+    std::vector<size_t> in_xy(n, 0), in_tri(n, 0);
+    size_t in_bytes = 0;
+    int max_nv = 0, max_nt = 0;
+    for (int i = 0; i < n; i++) {
+        out[i] = nullptr;
+        status[i] = GP_OK;
+        if (nv[i] < 0 || nt[i] < 0 || (nv[i] > 0 && !xy[i]) || (nt[i] > 0 && !tri[i])) status[i] = GP_EINVAL;
+        if (status[i] != GP_OK) continue;
+        max_nv = std::max(max_nv, nv[i]);
+        max_nt = std::max(max_nt, nt[i]);
+        if (in_dev) continue;
+        in_xy[i] = in_bytes;
+        in_bytes += align_up(8 * (size_t)nv[i], 16);
+        in_tri[i] = in_bytes;
+        in_bytes += align_up(12 * (size_t)nt[i], 16);
+    }
+    const size_t desc_off = align_up(in_bytes, 256), up_bytes = desc_off + sizeof(gp::SmallJob) * (size_t)n;
+    const size_t cnt_off = align_up(up_bytes, 256), cnt_bytes = 4 * (size_t)gp::kJobCounts * (size_t)n;
+    void *dev = nullptr;
+    int rc = c->pool.alloc(cnt_off + cnt_bytes, &dev);
+    char *up = rc == GP_OK ? static_cast<char *>(pinned_take(c, up_bytes)) : nullptr;
+    char *down = up ? static_cast<char *>(pinned_take(c, cnt_bytes)) : nullptr;
+    if (rc == GP_OK && (!up || !down)) rc = GP_ENOMEM;
+    char *d = static_cast<char *>(dev);
+    gp::SmallJob *descs = up ? reinterpret_cast<gp::SmallJob *>(up + desc_off) : nullptr;
+    std::vector<gp_mesh *> ms(n, nullptr);
+    for (int i = 0; i < n && rc == GP_OK; i++) {
+        gp::SmallJob &sj = descs[i];
+        sj = gp::SmallJob{};
+        sj.counts = reinterpret_cast<int32_t *>(d + cnt_off) + (size_t)gp::kJobCounts * i;
+        sj.build_only = 1;
+        if (status[i] != GP_OK) continue;   // nothing to build: an empty job in the launch
+        gp_mesh *m = new (std::nothrow) gp_mesh();
+        if (!m) {
+            status[i] = GP_ENOMEM;
+            continue;
+        }
+        ms[i] = m;
+        m->ctx = c;
+        m->nv = nv[i];
+        m->nt = nt[i];
+        const size_t nh = 3 * (size_t)nt[i];
+        void *p_xy = nullptr, *p_org = nullptr, *p_twin = nullptr;
+        int r = c->pool.alloc(sizeof(int2) * std::max<size_t>(nv[i], 1), &p_xy);
+        m->xy = static_cast<int2 *>(p_xy);
+        if (r == GP_OK) r = c->pool.alloc(sizeof(int32_t) * std::max<size_t>(nh, 1), &p_org);
+        m->org = static_cast<int32_t *>(p_org);
+        if (r == GP_OK) r = c->pool.alloc(sizeof(int32_t) * std::max<size_t>(nh, 1), &p_twin);
+        m->twin = static_cast<int32_t *>(p_twin);
+        if (r != GP_OK) {
+            status[i] = r;
+            continue;
+        }
+        if (in_dev) {
+            sj.xy = reinterpret_cast<const int2 *>(xy[i]);
+            sj.tri = tri[i];
+        } else {
+            if (nv[i]) std::memcpy(up + in_xy[i], xy[i], 8 * (size_t)nv[i]);
+            if (nt[i]) std::memcpy(up + in_tri[i], tri[i], 12 * (size_t)nt[i]);
+            sj.xy = reinterpret_cast<const int2 *>(d + in_xy[i]);
+            sj.tri = reinterpret_cast<const int32_t *>(d + in_tri[i]);
+        }
+        sj.nv = nv[i];
+        sj.nt = nt[i];
+        sj.org = m->org;
+        sj.twin = m->twin;
+        sj.xy_out = m->xy;
+    }
+    hipStream_t s = c->stream;
+    if (rc == GP_OK &&
+        (hipMemcpyAsync(d, up, up_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+         gp::launch_small_jobs(reinterpret_cast<const gp::SmallJob *>(d + desc_off), n, max_nv, max_nt, s) !=
+             hipSuccess ||
+         hipMemcpyAsync(down, d + cnt_off, cnt_bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess)) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        rc = GP_EHIP;
+    }
+    for (int i = 0; i < n; i++) {
+        gp_mesh *m = ms[i];
+        if (!m) {
+            if (rc != GP_OK && status[i] == GP_OK) status[i] = rc;
+            continue;
+        }
+        int st = rc != GP_OK ? rc : status[i];
+        if (st == GP_OK) {
+            const int32_t *cnt = reinterpret_cast<const int32_t *>(down) + (size_t)gp::kJobCounts * i;
+            const uint64_t key = (uint64_t)(uint32_t)cnt[8] | ((uint64_t)(uint32_t)cnt[9] << 32);
+            if (key != ~0ull) {
+                st = -(int)(key & 0xff);
+            } else {
+                m->nflipped = cnt[10];
+                m->bytes = align_up(sizeof(int2) * (size_t)std::max(m->nv, 1)) +
+                           2 * align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(3ll * m->nt, 1));
+                if (flags & GP_COMPACT) st = compact_mesh(c, m, reinterpret_cast<int32_t *>(down) + (size_t)gp::kJobCounts * i);
+            }
+        }
+        status[i] = st;
+        if (st == GP_OK) {
+            out[i] = m;
+        } else {
+            gpolylla_mesh_free(m);   // the stream has drained: nothing reads it
+        }
+    }
+    if (up) pinned_give(c, up, up_bytes);
+    if (down) pinned_give(c, down, cnt_bytes);
+    if (dev) c->pool.release(dev);
+    return GP_OK;
+}
+
 int build_many(gp_ctx *c, int n, const int32_t *const *xy, const int32_t *nv, const int32_t *const *tri,
                const int32_t *nt, uint32_t flags, gp_mesh **out, int *status) {
+    if (!(flags & GP_RENUMBER) && n > 0 && n < 65536 && c->cfg.small_max > 0) {
+        bool small = true;
+        int max_nv = 0, max_nt = 0;
+        for (int i = 0; i < n && small; i++) {
+            small = nv[i] >= 0 && nt[i] >= 0 && nv[i] <= gp::kJobSmallV && nt[i] <= std::min(gp::kJobSmallTri, c->cfg.small_max);
+            max_nv = std::max(max_nv, nv[i]);
+            max_nt = std::max(max_nt, nt[i]);
+        }
+        if (small && gp::small_job_lds_bytes(max_nv, max_nt) <= (size_t)c->cfg.lds_max)
+            return build_small_many(c, n, xy, nv, tri, nt, flags, out, status);
+    }
     std::vector<BuildJob> jobs(n);
     const size_t hb = 16 * (size_t)std::max(n, 1);
     char *host = static_cast<char *>(pinned_take(c, hb));
