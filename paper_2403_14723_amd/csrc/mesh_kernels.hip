@@ -107,9 +107,11 @@ __device__ __forceinline__ int he_prev(int h) {
     return (h - 3 * t == 0) ? h + 2 : h - 1;
 }
 
+// Coordinates lie in [0, 2^30] (the build checks them), so a difference fits
+// 32 bits and each square is one signed 32 x 32 -> 64-bit multiply.
 __device__ __forceinline__ long long sq_len(int2 a, int2 b) {
-    long long dx = (long long)b.x - a.x, dy = (long long)b.y - a.y;
-    return dx * dx + dy * dy;
+    const int dx = b.x - a.x, dy = b.y - a.y;
+    return (long long)dx * dx + (long long)dy * dy;
 }
 
 __device__ __forceinline__ bool fbit(uint32_t f, int i) { return (f >> (2 + i)) & 1u; }
