@@ -28,6 +28,7 @@ WORKLOADS = {
     "plain_1024x1024": "plain_scale",
     "plain_32x32": "plain_small",
     "delaunay1000000_s21m": "delaunay_1m",
+    "delaunay4000000_s21m": "delaunay_4m",
 }
 
 

@@ -250,6 +250,15 @@ def delaunay_1m() -> Mesh:
     return random_delaunay(1_000_000, 21, order="morton")
 
 
+def delaunay_4m() -> Mesh:
+    """Delaunay triangulation of 4M seeded random points, numbered along a
+    Z-order curve: the general-position workload at the size of the paper's
+    third Random mesh (Section 7.1, appendix tables; about 8M triangles).
+    Qhull takes minutes for it (the points snapped onto the sides are
+    collinear), so it is not part of the default benchmark run."""
+    return random_delaunay(4_000_000, 21, order="morton")
+
+
 def plain_large_warped() -> Mesh:
     """4096 x 4096 cells with the Gaussian-bump warp: 33,554,432 triangles."""
     return jittered_grid(4096, seed=2, warp=True, name="plain_4096x4096_warped")
