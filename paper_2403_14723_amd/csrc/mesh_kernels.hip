@@ -460,11 +460,14 @@ __device__ __forceinline__ int turn_step(const TileLabels &T, int &c, int &Lc, b
         if (g < 0) return -1;   // a non-frontier edge is interior
     } else {
         g = T.twin[c];
+        const uint32_t fc = Lc < 0 ? T.tflag[tc] : 0u;   // in flight with the twin
         if (g < 0) return 1;   // boundary
-        if (Lc < 0) Lc = (int)(T.tflag[tc] & 3u);
+        if (Lc < 0) Lc = (int)(fc & 3u);
         if (Lc != lc) {   // c is not its triangle's longest edge
-            const int tg = tri_of(g);
-            Lg = (int)(T.tflag[tg] & 3u);
+            // twin(c)'s triangle is often back in the tile, whose label
+            // bytes (longest-edge bits unchanged) are in LDS
+            const int tg = tri_of(g), kg = tg - T.base;
+            Lg = (int)(((unsigned)kg < (unsigned)T.cnt ? (uint32_t)T.s_f[kg] : (uint32_t)T.tflag[tg]) & 3u);
             if (Lg != g - 3 * tg) return 1;   // nor is twin(c)
         }
     }
