@@ -53,3 +53,14 @@ def test_cpu_baseline_reports_its_host():
     assert cpu["cores"] == 1 and cpu["core"] in before and cpu["nproc"] >= 1
     assert cpu["cpu_model"] and "march=native" in cpu["compiler"]
     assert cpu["value"] > 0 and res.stats["npoly"] > 0
+
+
+def test_every_workload_has_a_generator():
+    """Each --workload name maps to a generator in the workloads module, and
+    the Delaunay names carry their point counts."""
+    b = _bench()
+    from paper_2403_14723_amd import workloads as W
+    for name, fn in b.WORKLOADS.items():
+        assert callable(getattr(W, fn, None)), (name, fn)
+    assert b.WORKLOADS["delaunay1000000_s21m"] == "delaunay_1m"
+    assert b.WORKLOADS["delaunay4000000_s21m"] == "delaunay_4m"
