@@ -17,7 +17,7 @@
 namespace gp {
 
 constexpr int kWave = 64;
-constexpr int kPlMax = 63;            // loop lengths >= 63 are re-counted when emitted
+constexpr int kPlMax = 63;            // loop lengths >= 63: k_walk keeps them in lpos
 constexpr int kRotGuard = 1 << 20;    // bound on turns around one vertex
 
 // error bits collected on the device
@@ -57,6 +57,7 @@ struct MeshDesc {
     int32_t *loop_off;
     int32_t *loop_he;
     int32_t *lpos;       // per triangle: where k_walk stored the loop whose minimum it holds
+                         // (or that loop's length, when it is kPlMax or longer)
     MeshCounters *ctr;
     int32_t nt;
     int32_t nv;

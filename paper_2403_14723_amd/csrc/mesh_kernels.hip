@@ -1247,6 +1247,9 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
                 if (!closed[j]) continue;
                 const MeshDesc &d = descs[mesh[j]];
                 const bool won = claim_won(d, claim[j], mn[j], len[j], agg, cmp_tb);
+                // a loop too long for its length code is never stored, so its
+                // minimum's lpos slot is free: its length goes there for k_compact
+                if (won && len[j] >= kPlMax) ((gint)d.lpos)[tri_of(mn[j])] = len[j];
                 if (won && need[j] && room) {
                     const gint out = (gint)wbuf + pos;
                     out[0] = rot[j];
@@ -1264,19 +1267,6 @@ __global__ void __launch_bounds__(256) k_walk(const MeshDesc *__restrict__ descs
             if (!__any(active)) break;
         }
     }
-}
-
-// Length of the loop starting at mn (when it did not fit in the byte).
-__device__ __forceinline__ int loop_length(const MeshDesc &d, int mn) {
-    const gcint nx = (gcint)d.next_o;
-    const int nh = 3 * d.nt;
-    int cur = mn, len = 0;
-    do {
-        ++len;
-        cur = nx[cur];
-        if (cur < 0 || len > nh) return -1;
-    } while (cur != mn);
-    return len;
 }
 
 // The loops k_compact left out, each written from its minimum at its offset
@@ -1504,7 +1494,8 @@ __global__ void __launch_bounds__(1024) k_compact(const MeshDesc *__restrict__ d
         if (!code[j]) continue;
         int len = code[j] >> 2;
         if (len == kPlQuadNext) len = 4;
-        if (len >= kPlMax) len = loop_length(d, 3 * (t0 + j) + (code[j] & 3));
+        // longer than the code holds: k_walk left the length in lpos
+        if (len >= kPlMax) len = lp[j] >= kPlMax && lp[j] <= nh ? lp[j] : -1;
         if (len <= 0) {
             bad = true;
             len = 0;
