@@ -293,3 +293,48 @@ def two_grids(n1: int, n2: int, seed: int):
     xy = np.concatenate([a.xy, b.xy + shift]).astype(np.int32)
     tri = np.concatenate([a.tri, b.tri + a.nv]).astype(np.int32)
     return xy, tri, 2
+
+
+def rising_strip(n: int, top_end: bool, x0: int = 0, y0: int = 0, h: int = 1000):
+    """A strip of triangles between a bottom row b_i = (4i, 0), i = 0..n, and
+    a rising top row t_i = (4i + 1, h + i), whose every triangle has a
+    unique longest edge: the rung on its right.  Rung lengths grow strictly
+    along the strip (t_i - b_i shorter than b_{i+1} - t_i at the same
+    height, the next rung one unit higher), so each inner rung is the
+    longest edge of exactly one side (not frontier) and the last rung is
+    the longest edge of the last triangle and on the boundary (terminal).
+    The strip is one polygon whose loop is its whole boundary: 2n + 1
+    half-edges, or 2n + 2 with top_end (a last top triangle closing the
+    strip at t_n).  Returns xy, tri (counter-clockwise, bottom and top
+    triangles alternating)."""
+    nb = n + 1
+    nt_top = n + 1 if top_end else n
+    bx = 4 * np.arange(nb)
+    xy = np.concatenate([np.stack([bx, np.zeros(nb, np.int64)], -1),
+                         np.stack([4 * np.arange(nt_top) + 1, h + np.arange(nt_top)], -1)])
+    xy = xy + np.array([x0, y0])
+    b = np.arange(nb)
+    t = nb + np.arange(nt_top)
+    bottom = np.stack([b[:n], b[1:], t[:n]], -1)                  # (b_i, b_{i+1}, t_i)
+    ntop = n if top_end else n - 1
+    top = np.stack([t[:ntop], b[1:ntop + 1], t[1:ntop + 1]], -1)   # (t_i, b_{i+1}, t_{i+1})
+    tri = np.empty((len(bottom) + len(top), 3), np.int64)
+    tri[0::2] = bottom
+    tri[1::2] = top
+    return xy.astype(np.int32), tri.astype(np.int32)
+
+
+def rising_strips(cases):
+    """Several rising strips (each (n, top_end)) stacked without shared
+    vertices: one polygon per strip, with loops of 2n + 1 or 2n + 2
+    half-edges.  Returns xy, tri, chi (the strip count: one disk each) and
+    the loop lengths in strip order."""
+    xys, tris, lens, nv, y0 = [], [], [], 0, 0
+    for n, top_end in cases:
+        xy, tri = rising_strip(n, top_end, 0, y0)
+        xys.append(xy)
+        tris.append(tri + nv)
+        nv += len(xy)
+        y0 += 1000 + n + 64
+        lens.append(2 * n + (2 if top_end else 1))
+    return np.concatenate(xys).astype(np.int32), np.concatenate(tris).astype(np.int32), len(cases), lens

@@ -387,6 +387,20 @@ def test_hole_and_two_components(ctx, case):
                     chi=chi)
 
 
+def test_loops_longer_than_the_length_code(ctx):
+    """One polygon per rising strip, loops of 62 to 66, 127, 1,001 and 4,001
+    half-edges (5,433 triangles, so the tiled chain runs): the walk, the
+    lengths of loops longer than a loop byte holds, and the emitted loops,
+    against the oracle."""
+    cases = [(30, True), (31, False), (31, True), (32, False), (32, True), (63, False), (500, False), (2000, False)]
+    xy, tri, chi, lens = pc.rising_strips(cases)
+    assert len(tri) > 4096
+    g, o = check_case(ctx, xy, tri, "rising_strips")
+    np.testing.assert_array_equal(np.diff(g["loop_off"]), lens)
+    pc.check_output(xy, g["org"], g["twin"], g["next"], g["prev"], g["seeds"], g["loop_off"], g["loop_he"],
+                    chi=chi)
+
+
 def test_pool_exhaustion_is_an_error_and_the_context_recovers():
     """A context whose device pool is capped refuses a mesh that does not fit
     with GP_ENOMEM (nothing is launched for it) and still meshes one that

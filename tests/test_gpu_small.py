@@ -48,6 +48,9 @@ def _corpus():
                           name))
     xy, tri, _ = pc.grid_with_hole(40, 17, 12)
     out.append(W.Mesh(xy, tri, "hole40"))
+    # loops of 62, 63, 127 and 1,001 half-edges (a loop byte holds up to 62)
+    xy, tri, _, _ = pc.rising_strips([(30, True), (31, False), (63, False), (500, False)])
+    out.append(W.Mesh(xy, tri, "rising_strips"))
     return out
 
 

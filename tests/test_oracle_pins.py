@@ -283,3 +283,18 @@ def test_scrambled_is_the_same_triangulation(seed):
     assert a.stats["nties"] == 0 and 0 < b.stats["nflipped"] < s.nt
     assert b.stats["npoly"] == a.stats["npoly"] and b.stats["nloop_he"] == a.stats["nloop_he"]
     pc.check_output(s.xy, b.org, b.twin, b.next, b.prev, b.seeds, b.loop_off, b.loop_he)
+
+
+def test_rising_strips_one_polygon_each():
+    """Closed form: a strip whose rungs grow strictly along it is one polygon
+    (each inner rung is the longest edge of exactly one side, the last rung
+    terminal), with its whole boundary as the loop: 2n + 1 half-edges, or
+    2n + 2 when a top triangle closes it.  Loops of 62 to 66 half-edges sit
+    either side of the longest length a loop byte holds (62)."""
+    cases = [(30, True), (31, False), (31, True), (32, False), (32, True), (63, False), (500, False)]
+    xy, tri, chi, lens = pc.rising_strips(cases)
+    o = oracle.polylla(xy, tri)
+    assert o.stats["npoly"] == len(cases) and o.stats["ntips"] == 0
+    np.testing.assert_array_equal(np.diff(o.loop_off), lens)
+    assert o.stats["nloop_he"] == sum(lens)
+    pc.check_output(xy, o.org, o.twin, o.next, o.prev, o.seeds, o.loop_off, o.loop_he, chi=chi)
