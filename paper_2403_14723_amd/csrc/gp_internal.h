@@ -146,6 +146,7 @@ struct RunBuffers {
 // k_walk records each chain's half-edges in LDS, up to this many; longer
 // loops are left to k_emit
 constexpr int kWalkBuf = 16;
+constexpr long long kStreamOutBytes = 256ll << 20;   // MI355X's last-level cache (Infinity Cache)
 constexpr int kWalkItems = 1;   // chains per k_walk thread
 constexpr int kTileScanItems = 4;                   // compaction tiles per k_tile_scan thread
 constexpr int kScanChunk = 1024 * kTileScanItems;   // compaction tiles per k_tile_scan block

@@ -525,8 +525,9 @@ __device__ __forceinline__ bool outside_fbit(const TileLabels &T, int c, int Lc)
 }
 
 // CM: some mesh of the run is compact (else the int32 twins are read
-// without a test of the encoding)
-template <int ITEMS, bool CM>
+// without a test of the encoding).  NT: next'/prev' go out as streaming
+// (nontemporal) stores.
+template <int ITEMS, bool CM, bool NT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) k_relink(const MeshDesc *__restrict__ descs, int nmesh,
                                                   RunCounters *rc, ListEntry *tips, int cap_tips,
                                                   ListEntry *walk, int32_t *walk_counts, int walk_cap,
@@ -847,8 +848,14 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) 
             }
         }
         const int h0 = 3 * (base + lt);
-        *reinterpret_cast<GLOBAL v3i *>(nxo + h0) = v3i{nv3[j][0], nv3[j][1], nv3[j][2]};
-        *reinterpret_cast<GLOBAL v3i *>(pvo + h0) = v3i{pv3[j][0], pv3[j][1], pv3[j][2]};
+        const v3i nv = v3i{nv3[j][0], nv3[j][1], nv3[j][2]}, pv = v3i{pv3[j][0], pv3[j][1], pv3[j][2]};
+        if (NT) {
+            __builtin_nontemporal_store(nv, reinterpret_cast<GLOBAL v3i *>(nxo + h0));
+            __builtin_nontemporal_store(pv, reinterpret_cast<GLOBAL v3i *>(pvo + h0));
+        } else {
+            *reinterpret_cast<GLOBAL v3i *>(nxo + h0) = nv;
+            *reinterpret_cast<GLOBAL v3i *>(pvo + h0) = pv;
+        }
     }
     // the tile's label and loop bytes in whole words (the label bytes keep
     // their longest-edge bits, which other tiles may be reading)
@@ -2358,20 +2365,31 @@ hipError_t launch_export_counts(const MeshCounters *c, int32_t *out, hipStream_t
         }                                                                                     \
     } while (0)
 
-template <bool CM>
-hipError_t launch_relink(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, size_t lds, int cmp_tb) {
+template <bool CM, bool NT>
+hipError_t launch_relink_nt(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, size_t lds, int cmp_tb) {
     const dim3 grid(rb.he_tiles), block(cfg.block_relink);
 #define GP_RELINK_ARGS rb.descs, rb.nmesh, rb.rc, rb.tips, rb.cap_tips, rb.walk, rb.walk_counts, rb.walk_cap, \
                        rb.status, cmp_tb
     switch (cfg.items_relink) {
-        case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<1, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
-        case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<2, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
-        case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<4, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
-        case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<8, CM>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 1: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<1, CM, NT>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 2: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<2, CM, NT>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 4: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<4, CM, NT>), grid, block, lds, s, GP_RELINK_ARGS); break;
+        case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(k_relink<8, CM, NT>), grid, block, lds, s, GP_RELINK_ARGS); break;
         default: return hipErrorInvalidValue;
     }
 #undef GP_RELINK_ARGS
     return hipGetLastError();
+}
+
+// next'/prev' of a run larger than the last-level cache go out as streaming
+// stores: they would not stay cached for the kernels that read them, and the
+// cache keeps what those kernels reuse (the run's size from its label tiles,
+// at most a tile per mesh over).  Smaller runs keep them cached.
+template <bool CM>
+hipError_t launch_relink(const LaunchCfg &cfg, const RunBuffers &rb, hipStream_t s, size_t lds, int cmp_tb) {
+    const bool stream_out = 24ll * rb.tri_tiles * cfg.block_label * cfg.items_label > kStreamOutBytes;
+    return stream_out ? launch_relink_nt<CM, true>(cfg, rb, s, lds, cmp_tb)
+                      : launch_relink_nt<CM, false>(cfg, rb, s, lds, cmp_tb);
 }
 
 bool small_fits(const LaunchCfg &cfg, int max_nt) {
